@@ -1,0 +1,406 @@
+"""FP64 CPU oracle for the fault-tolerant batched FFT (TEST INFRASTRUCTURE).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the HIP library
+and never calls it; the product never calls it either.
+
+Parts (each cites the passage of the TurboFFT paper, arXiv 2405.02520, that it
+writes out):
+
+* ``omega``/``dft_naive``/``fft``/``ifft`` -- Section II, the DFT and inverse
+  DFT definitions (inverse carries 1/N) and the DFT as the product of the DFT
+  matrix W = (w_N^{jk}) with the signal; ``fft`` is the textbook recursive
+  radix-2 factorisation of the same W, in C (``tfft_oracle.c``).
+* ``encoding_vector``/``checksum_vector`` -- Section II-C, Eq. (1)-(2): the
+  per-position encoding vector e (Wang's choice e_k = w_3^k, which leaves the
+  input unchanged) and the precomputed left checksum c = (e^T W)^T.
+* ``two_sided_group`` -- Section III, Eq. (4)-(5) and III-B: one batch of G
+  signals X is encoded with the batch vectors w1 = (1, ..., 1) and
+  w2 = (1, 2, ..., G); the pre-transform checksums (e^T W)(X w) are compared
+  with the post-transform checksums e^T (Y w); the quotient of the two
+  residuals locates the corrupted signal; the divergence between the transform
+  of the combined input, W (X w1), and the combined output, Y w1, is added
+  back to it.
+* ``fourstep`` -- Section IV-A.1 (tiled FFT): a length N1*N2 transform as N2
+  column transforms, a twiddle, and N1 row transforms whose outputs are stored
+  transposed.  Used to state the per-pass checksum domains of a two-pass plan.
+
+Readings where the paper is silent are listed in the module docstring of
+``two_sided_group`` and in the design notes.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tfft_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libtfft_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C part of the oracle (gcc, -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Fault(ctypes.Structure):
+    """Additive fault on the output of one node of the radix-2 recursion."""
+
+    _fields_ = [
+        ("level", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("node", ctypes.c_int64),
+        ("index", ctypes.c_int64),
+        ("dre", ctypes.c_double),
+        ("dim", ctypes.c_double),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_omega.argtypes = [ctypes.c_int64, ctypes.c_int64, dp, dp]
+        L.orc_omega_table.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+        for name in ("orc_dft_naive_batch", "orc_fft_batch"):
+            getattr(L, name).argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int, ctypes.c_int]
+            getattr(L, name).restype = ctypes.c_int
+        L.orc_fft_faulty.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                     ctypes.POINTER(Fault), ctypes.c_int64]
+        L.orc_fft_faulty.restype = ctypes.c_int
+        L.orc_max_threads.restype = ctypes.c_int
+        L.orc_fault_struct_size.restype = ctypes.c_int
+        assert L.orc_fault_struct_size() == ctypes.sizeof(Fault)
+        _lib = L
+    return _lib
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+# ----------------------------------------------------------------- the DFT
+
+def omega(t, n: int) -> np.ndarray:
+    """w_n^t = exp(-2 pi i t / n) for an integer array t (exact angle reduction)."""
+    t = np.asarray(t, dtype=np.int64)
+    flat = np.mod(t.ravel(), n)
+    out = np.empty(flat.size, dtype=np.complex128)
+    if flat.size:
+        table = omega_table(n, int(flat.max()) + 1)
+        out[:] = table[flat]
+    return out.reshape(t.shape)
+
+
+def omega_table(n: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.complex128)
+    lib().orc_omega_table(n, count, out.ctypes.data)
+    return out
+
+
+def _as_batch(x) -> tuple[np.ndarray, tuple]:
+    x = np.asarray(x)
+    shape = x.shape
+    xb = np.ascontiguousarray(x.reshape(-1, shape[-1]), dtype=np.complex128)
+    return xb, shape
+
+
+def dft_naive(x, inverse: bool = False, threads: int = 0) -> np.ndarray:
+    """Direct O(N^2) evaluation of the DFT along the last axis (inverse: 1/N)."""
+    xb, shape = _as_batch(x)
+    n = shape[-1]
+    y = np.empty_like(xb)
+    rc = lib().orc_dft_naive_batch(xb.ctypes.data, y.ctypes.data, n, xb.shape[0], 1 if inverse else -1, threads)
+    if rc != 0:
+        raise ValueError(f"orc_dft_naive_batch failed ({rc})")
+    if inverse:
+        y /= n
+    return y.reshape(shape)
+
+
+def fft(x, inverse: bool = False, scale: float | None = None, threads: int = 0) -> np.ndarray:
+    """Radix-2 FFT along the last axis.  ``inverse`` uses w^{-jk}; the result is
+    multiplied by ``scale`` (default 1 forward, 1/N inverse)."""
+    xb, shape = _as_batch(x)
+    n = shape[-1]
+    y = np.empty_like(xb)
+    rc = lib().orc_fft_batch(xb.ctypes.data, y.ctypes.data, n, xb.shape[0], 1 if inverse else -1, threads)
+    if rc != 0:
+        raise ValueError(f"orc_fft_batch failed ({rc}); n must be a power of two")
+    s = (1.0 / n if inverse else 1.0) if scale is None else scale
+    if s != 1.0:
+        y *= s
+    return y.reshape(shape)
+
+
+def ifft(y, threads: int = 0) -> np.ndarray:
+    return fft(y, inverse=True, threads=threads)
+
+
+def fft_faulty(x, faults, inverse: bool = False) -> np.ndarray:
+    """Unscaled radix-2 transform of ONE signal with additive faults on the
+    outputs of recursion nodes; ``faults`` = [(level, node, index, complex delta)]."""
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    n = x.shape[-1]
+    arr = (Fault * max(1, len(faults)))()
+    for i, (lvl, node, idx, d) in enumerate(faults):
+        arr[i] = Fault(int(lvl), 0, int(node), int(idx), float(np.real(d)), float(np.imag(d)))
+    y = np.empty_like(x)
+    rc = lib().orc_fft_faulty(x.ctypes.data, y.ctypes.data, n, 1 if inverse else -1, arr, len(faults))
+    if rc != 0:
+        raise ValueError(f"orc_fft_faulty failed ({rc})")
+    return y
+
+
+# ------------------------------------------------------- checksum vectors
+
+W3 = complex(-0.5, -math.sqrt(3.0) / 2.0)  # w_3 = exp(-2 pi i / 3)
+
+
+def encoding_vector(m: int) -> np.ndarray:
+    """e_k = w_3^k, k = 0..m-1 (Wang's vector, Section II-C), from the exact
+    three-point table."""
+    table = omega_table(3, 3)
+    return table[np.arange(m) % 3]
+
+
+def checksum_vector(m: int, inverse: bool = False, scale: float = 1.0) -> np.ndarray:
+    """c = scale * (e^T W)^T for e = w_3^k, in closed form.
+
+    sum_k w_3^k a^k is geometric with ratio a = w_3 w_m^{+-n}; because
+    w_m^{n m} = 1 its sum is (1 - w_3^m) / (1 - w_3 w_m^{+-n}), never 0/0 for a
+    power-of-two m (m is not a multiple of 3)."""
+    n = np.arange(m, dtype=np.int64)
+    wn = omega(n, m)
+    if inverse:
+        wn = np.conj(wn)
+    w3 = omega_table(3, 3)
+    w3m = w3[m % 3]
+    return scale * (1.0 - w3m) / (1.0 - w3[1] * wn)
+
+
+def checksum_vector_direct(m: int, inverse: bool = False, scale: float = 1.0, e=None) -> np.ndarray:
+    """c_n = scale * sum_k e_k w_m^{+-k n}, summed term by term."""
+    if e is None:
+        e = encoding_vector(m)
+    k = np.arange(m, dtype=np.int64)
+    w = omega(np.outer(k, k) % m, m)
+    if inverse:
+        w = np.conj(w)
+    return scale * (e[:, None] * w).sum(axis=0)
+
+
+def threshold(m: int, s: float, kappa: float, u: float) -> float:
+    """tau = kappa * u * sqrt(log2 m) * sqrt(m * S), S = sum over the group of |x|^2.
+
+    The paper tests the relative residual against a threshold delta picked from
+    its ROC study and prints no value; this norm form scales with the expected
+    rounding noise of a length-m FFT on inputs of energy S."""
+    return kappa * u * math.sqrt(max(1.0, math.log2(m))) * math.sqrt(m * s)
+
+
+# ------------------------------------------------------- two-sided checksum
+
+CORRECTED = "corrected"
+DETECTED = "detected"
+BENIGN = "benign"
+UNCORRECTABLE = "uncorrectable"
+
+
+@dataclass
+class GroupRecord:
+    group: int
+    flagged: bool
+    d1: complex
+    d2: complex
+    tau: float
+    s: float
+    rho: complex
+    located: int = -1          # member index j within the group, -1 if none
+    method: str = ""           # "quotient" | "per-signal" | ""
+    action: str = ""           # CORRECTED | DETECTED | BENIGN | UNCORRECTABLE | ""
+    extra: dict = field(default_factory=dict)
+
+
+def _locate_by_quotient(d1: complex, d2: complex, g: int) -> tuple[int, complex]:
+    with np.errstate(all="ignore"):
+        rho = d2 / d1 if d1 != 0 else complex(np.nan, np.nan)
+    if not (np.isfinite(rho.real) and np.isfinite(rho.imag)):
+        return -1, rho
+    j = int(math.floor(rho.real + 0.5)) - 1
+    if 0 <= j < g and abs(rho - (j + 1)) <= 0.25:
+        return j, rho
+    return -1, rho
+
+
+def two_sided_group(X, Yhat, *, inverse=False, scale=1.0, kappa=16.0, u=2.0 ** -24, mode="correct",
+                    e=None, out_twiddle=None, group=0, per_signal_fallback=True, r1_fault=0.0):
+    """Two-sided checksum of one group (Section III, Eq. (4)-(5), III-B).
+
+    X      [G, M] the G input signals of the group (row b is signal b; the
+           paper's X is this matrix transposed, one signal per column).
+    Yhat   [G, M] the outputs as produced (by any implementation, possibly
+           faulty), already multiplied by ``out_twiddle`` if given.
+    The transform is Y = scale * W X (W with w^{-jk} when ``inverse``).
+    out_twiddle [G, M] unit twiddles applied to each output after the
+           transform (first pass of a two-pass plan); the output checksum then
+           uses e' = e * conj(twiddle) so the twiddle product is inside the
+           checked region.
+    r1_fault  a value added to the post-transform checksum R1 (a fault in the
+           checksum arithmetic itself), for tests.
+
+    Returns (corrected outputs [G, M], GroupRecord).
+
+    Readings (the paper does not state them):
+      * e = w_3^k (Wang) for the per-position vector; batch vectors w1 = 1,
+        w2 = (1..G), one-based so that signal 0 is not weighted by zero;
+      * detection threshold: ``threshold``; the test !(|d1| <= tau) also flags NaN;
+      * location j = round(Re(d2/d1)) - 1, accepted iff 0 <= j < G and
+        |d2/d1 - (j+1)| <= 1/4; else, when enabled, the per-signal residuals
+        e'_b . y_b - c . x_b locate the signal if exactly one exceeds its own
+        threshold;
+      * correction: y_j <- W(X w1) - sum_{b != j} y_b, algebraically the
+        paper's "add the divergence back" y_j + (W(X w1) - Y w1) but free of
+        cancellation when the fault is huge or not finite;
+      * no location: the group is benign if ||W(X w1) - Y w1||_2 <= tau (the
+        data agree; the fault hit the checksum arithmetic), else uncorrectable.
+    """
+    X = np.asarray(X, dtype=np.complex128)
+    Y = np.array(Yhat, dtype=np.complex128)
+    G, M = X.shape
+    if e is None:
+        e = encoding_vector(M)
+        c = checksum_vector(M, inverse, scale)
+    else:
+        e = np.asarray(e, dtype=np.complex128)
+        c = checksum_vector_direct(M, inverse, scale, e)
+    if out_twiddle is None:
+        ep = np.broadcast_to(e, (G, M))
+        untw = np.ones((G, M), dtype=np.complex128)
+    else:
+        tw = np.asarray(out_twiddle, dtype=np.complex128)
+        ep = e[None, :] * np.conj(tw)
+        untw = np.conj(tw)
+    w1 = np.ones(G)
+    w2 = np.arange(1, G + 1, dtype=np.float64)
+
+    # Eq. (4): X^c = [X, X e_batch] -- the batch-encoded columns X w1, X w2
+    xw1 = (w1[:, None] * X).sum(axis=0)
+    xw2 = (w2[:, None] * X).sum(axis=0)
+    # Eq. (5), bottom row: (e^T W)(X w) before the transform
+    L1 = complex(np.dot(c, xw1))
+    L2 = complex(np.dot(c, xw2))
+    # ... and e^T (Y w) after it
+    with np.errstate(all="ignore"):
+        per_sig = (ep * Y).sum(axis=1)
+        R1 = complex(np.dot(w1, per_sig)) + r1_fault
+        R2 = complex(np.dot(w2, per_sig))
+    d1, d2 = R1 - L1, R2 - L2
+    S = float(np.sum(X.real ** 2 + X.imag ** 2))
+    tau = threshold(M, S, kappa, u)
+    flagged = not (abs(d1) <= tau)
+    j, rho = _locate_by_quotient(d1, d2, G)
+    rec = GroupRecord(group=group, flagged=flagged, d1=d1, d2=d2, tau=tau, s=S, rho=rho)
+    if not flagged:
+        return Y, rec
+    method = "quotient" if j >= 0 else ""
+    if j < 0 and per_signal_fallback:
+        with np.errstate(all="ignore"):
+            db = per_sig - X @ c
+            Sb = (X.real ** 2 + X.imag ** 2).sum(axis=1)
+            taub = np.array([threshold(M, float(sb), kappa, u) for sb in Sb])
+            bad = np.flatnonzero(~(np.abs(db) <= taub))
+        if bad.size == 1:
+            j, method = int(bad[0]), "per-signal"
+    rec.located, rec.method = j, method
+    if mode == "detect":
+        rec.action = DETECTED
+        return Y, rec
+    # III-B: transform of the combined input vs the combined output
+    P = fft(xw1, inverse=inverse, scale=scale)
+    if j >= 0:
+        with np.errstate(all="ignore"):
+            others = np.delete(untw * Y, j, axis=0).sum(axis=0)
+        Y[j] = (P - others) / untw[j]
+        rec.action = CORRECTED
+        return Y, rec
+    with np.errstate(all="ignore"):
+        dP = P - (untw * Y).sum(axis=0)
+        ok = bool(np.linalg.norm(dP) <= tau)
+    rec.action = BENIGN if ok else UNCORRECTABLE
+    return Y, rec
+
+
+def two_sided_batch(X, Yhat, G: int, **kw):
+    """Apply ``two_sided_group`` to consecutive groups of G signals (the last
+    group may be shorter).  Returns (outputs, [records of flagged groups])."""
+    X = np.asarray(X)
+    Yhat = np.asarray(Yhat)
+    B = X.shape[0]
+    out = np.array(Yhat, dtype=np.complex128)
+    recs = []
+    tw = kw.pop("out_twiddle", None)
+    for g0 in range(0, B, G):
+        sl = slice(g0, min(B, g0 + G))
+        twg = None if tw is None else tw[sl]
+        y, rec = two_sided_group(X[sl], Yhat[sl], out_twiddle=twg, group=g0 // G, **kw)
+        out[sl] = y
+        if rec.flagged:
+            recs.append(rec)
+    return out, recs
+
+
+# ------------------------------------------------------------ four-step
+
+def interpass_twiddle(n1: int, n2: int, inverse: bool = False) -> np.ndarray:
+    """tw[k1, n2] = w_N^{k1 n2} (conjugated for the inverse), N = n1 * n2."""
+    n = n1 * n2
+    k1 = np.arange(n1, dtype=np.int64)[:, None]
+    m2 = np.arange(n2, dtype=np.int64)[None, :]
+    tw = omega((k1 * m2) % n, n)
+    return np.conj(tw) if inverse else tw
+
+
+def fourstep(x, n1: int, n2: int, inverse: bool = False, scale: float | None = None):
+    """Length N = n1*n2 transform of each row of x as two passes (Section IV-A.1).
+
+    x[n1_ * n2 + n2_] is viewed as an n1 x n2 matrix.  Pass 1 transforms each
+    column (length n1) and multiplies by the twiddle w_N^{k1 n2}; pass 2
+    transforms each row (length n2) and the result is stored transposed,
+    y[k1 + n1 * k2].  Returns dict(mid=[B, n1, n2] pass-1 output,
+    out=[B, n1, n2] pass-2 output before the transposed store, y=[B, N],
+    tw=[n1, n2]).  ``scale`` (default 1/N for the inverse) is applied in pass 2."""
+    x = np.asarray(x, dtype=np.complex128)
+    B = x.shape[0]
+    n = n1 * n2
+    s = (1.0 / n if inverse else 1.0) if scale is None else scale
+    a = x.reshape(B, n1, n2)
+    cols = np.ascontiguousarray(np.transpose(a, (0, 2, 1)))       # [B, n2, n1]
+    colf = fft(cols, inverse=inverse, scale=1.0)
+    tw = interpass_twiddle(n1, n2, inverse)
+    mid = np.transpose(colf, (0, 2, 1)) * tw[None]                  # [B, n1, n2]
+    out = fft(np.ascontiguousarray(mid), inverse=inverse, scale=s)  # rows
+    y = np.ascontiguousarray(np.transpose(out, (0, 2, 1))).reshape(B, n)
+    return dict(mid=np.ascontiguousarray(mid), out=out, y=y, tw=tw)
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))

@@ -1,0 +1,74 @@
+"""Seeded synthetic signal generators shared by the tests, the smoke check and
+the benchmark.
+
+This module holds no transform or checksum arithmetic: it only draws numbers.
+Both the oracle side and the HIP side receive their inputs from here, so that
+they see bit-identical data.
+
+Recipe (the paper measures on random signals, "generated with normal
+distribution" in its fault-coverage study, and batched sizes with N*batch held
+at 2^28 elements in its throughput study):
+
+* ``uniform``: re and im i.i.d. U[-1, 1), drawn as two separate arrays, real
+  part first, from ``numpy.random.default_rng(seed)`` (PCG64).
+* ``gaussian``: re and im i.i.d. N(0, 1), same order.
+* ``dynamic``: |x| = exp(sigma * Z), Z ~ N(0, 1), sigma = ln(1e6) / 6 (so that
+  +-3 sigma spans six decades), phase ~ U[0, 2 pi); magnitudes first.
+
+Fault positions come from a separate stream, ``default_rng(seed ^ 0xFA17)``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SEED_CORRECTNESS = 20240501
+SEED_SWEEP = 20240502
+SEED_PRECISION = 20240503
+SEED_RAGGED = 20240504
+SEED_GRAD = 20240505
+FAULT_SEED_XOR = 0xFA17
+
+
+def sweep_seed(log2n: int, fp64: bool) -> int:
+    return SEED_SWEEP + log2n + (100 if fp64 else 0)
+
+
+def precision_seed(log2n: int, dynamic: bool) -> int:
+    return SEED_PRECISION + log2n + (1000 if dynamic else 0)
+
+
+def fault_rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed ^ FAULT_SEED_XOR)
+
+
+def _as_complex(re: np.ndarray, im: np.ndarray, dtype) -> np.ndarray:
+    dtype = np.dtype(dtype)
+    real = np.float32 if dtype == np.complex64 else np.float64
+    out = np.empty(re.shape, dtype=dtype)
+    out.real = re.astype(real)
+    out.imag = im.astype(real)
+    return out
+
+
+def uniform(seed: int, batch: int, n: int, dtype=np.complex64) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    re = rng.uniform(-1.0, 1.0, size=(batch, n))
+    im = rng.uniform(-1.0, 1.0, size=(batch, n))
+    return _as_complex(re, im, dtype)
+
+
+def gaussian(seed: int, batch: int, n: int, dtype=np.complex64) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    re = rng.standard_normal(size=(batch, n))
+    im = rng.standard_normal(size=(batch, n))
+    return _as_complex(re, im, dtype)
+
+
+def dynamic(seed: int, batch: int, n: int, dtype=np.complex64) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    sigma = math.log(1e6) / 6.0
+    mag = np.exp(sigma * rng.standard_normal(size=(batch, n)))
+    phase = rng.uniform(0.0, 2.0 * math.pi, size=(batch, n))
+    return _as_complex(mag * np.cos(phase), mag * np.sin(phase), dtype)
