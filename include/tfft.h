@@ -1,0 +1,190 @@
+/*
+ * tfft.h -- C ABI of the fault-tolerant batched FFT library for MI355X (gfx950).
+ *
+ * The library computes a batched one-dimensional complex-to-complex discrete
+ * Fourier transform (TurboFFT paper, arXiv 2405.02520, Section II: forward
+ * y_j = sum_n x_n w_N^{jn}, w_N = exp(-2 pi i/N); inverse with w_N^{-jn} and
+ * a 1/N factor) and protects it with the paper's two-sided checksum
+ * (Section III, Eq. (4)-(5)): each group of G signals is encoded before the
+ * transform with the per-position vector c = (e^T W)^T and the batch vectors
+ * w1 = 1, w2 = (1..G); after it with e; a mismatch beyond a rounding-scaled
+ * threshold is detected, the quotient of the two residuals locates the
+ * corrupted signal, and the divergence between the transform of the combined
+ * input and the combined output is added back to it (Section III-B).
+ *
+ * Conventions for every entry point:
+ *  - Status codes are ints (enum tfft_status); nothing throws across the ABI.
+ *  - Device buffers are owned by the caller, hold `batch` contiguous signals of
+ *    `n` interleaved complex values (re, im) each, row-major [batch][n], and
+ *    must be 16-byte aligned.  Input and output must not overlap.
+ *  - A plan owns its tables, workspace and report buffers; it is bound to the
+ *    device current when it was created and must not be executed on two
+ *    streams at once.  hip_stream may be NULL (the null stream).
+ *  - Execution is asynchronous on the given stream; tfft_get_report
+ *    synchronises that stream.
+ */
+#ifndef TFFT_H
+#define TFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TFFT_VERSION 1
+
+typedef struct tfft_plan_s *tfft_plan;
+
+/* Element type: complex64 (two binary32) or complex128 (two binary64). */
+enum tfft_dtype { TFFT_C64 = 0, TFFT_C128 = 1 };
+
+/* Fault-tolerance mode of one execution.
+ *  OFF     transform only.
+ *  DETECT  transform + two-sided checksum; flagged groups are reported (and
+ *          located by the residual quotient) but outputs are left as computed.
+ *  CORRECT as DETECT, then the located signal of each flagged group is
+ *          rewritten from the transform of the group's combined input
+ *          (delayed, batched correction, Section III-B).                     */
+enum tfft_ft_mode { TFFT_FT_OFF = 0, TFFT_FT_DETECT = 1, TFFT_FT_CORRECT = 2 };
+
+enum tfft_status {
+    TFFT_OK = 0,
+    TFFT_UNCORRECTABLE = 1,  /* output written; some flagged group could not be located */
+    TFFT_E_INVALID = -1,     /* bad argument */
+    TFFT_E_UNSUPPORTED = -2, /* valid request this build does not implement */
+    TFFT_E_NOMEM = -3,       /* device or host allocation failed */
+    TFFT_E_HIP = -4,         /* a HIP runtime call failed */
+    TFFT_E_STATE = -5        /* call out of order (e.g. report before any exec) */
+};
+
+/* Plan flags. */
+enum tfft_flags {
+    TFFT_INVERSE_UNSCALED = 1u << 0 /* exec_inverse omits the 1/N factor */
+};
+
+/* Record actions. */
+enum tfft_action {
+    TFFT_ACT_DETECTED = 1,      /* flagged; DETECT mode */
+    TFFT_ACT_CORRECTED = 2,     /* flagged, located and rewritten */
+    TFFT_ACT_BENIGN = 3,        /* flagged, data consistent (fault hit the checksum) */
+    TFFT_ACT_UNCORRECTABLE = 4  /* flagged, not locatable (outside one fault per group) */
+};
+
+/* Location method of a record. */
+enum tfft_locate { TFFT_LOC_NONE = 0, TFFT_LOC_QUOTIENT = 1, TFFT_LOC_PER_SIGNAL = 2 };
+
+/* Options for tfft_plan_create_with.  Zero fields take the defaults. */
+typedef struct {
+    uint32_t flags;  /* enum tfft_flags */
+    int32_t group;   /* signals per checksum group G (a power of two, 1..64); 0 = default */
+    double kappa;    /* threshold factor; 0 = default (16) */
+    int32_t reserved[8];
+} tfft_options;
+
+/* Description of a plan (tfft_plan_info). */
+typedef struct {
+    int64_t n, batch;
+    int32_t dtype, passes;
+    int32_t pass_len[2];       /* transform length of each pass, product = n          */
+    int32_t group[2];          /* checksum group size of each pass                    */
+    int32_t elems_per_thread[2];
+    int32_t tile_signals[2];   /* signals held in LDS at once by one workgroup         */
+    int32_t stages[2];
+    int32_t radices[2][8];     /* butterfly radix of each stage of each pass           */
+    int64_t groups[2];         /* checksum groups per pass                             */
+    size_t workspace_bytes;
+    double kappa;
+} tfft_plan_desc;
+
+/* Counters of the last execution. */
+typedef struct {
+    int64_t groups_checked; /* groups whose checksums were compared (all passes) */
+    int64_t detected;       /* flagged groups                                    */
+    int64_t corrected;
+    int64_t uncorrectable;
+    int64_t benign;
+    int64_t n_records;      /* records available (<= capacity)                   */
+    int64_t dropped;        /* flagged groups beyond the record capacity         */
+} tfft_counts;
+
+/* One flagged group. */
+typedef struct {
+    int64_t signal;   /* batch index of the affected signal (group's first signal if not located) */
+    int64_t sub;      /* two-pass plans: column (pass 0) or row (pass 1) of the located member; else 0 */
+    int64_t group;    /* checksum group index within the pass */
+    int32_t pass;     /* 0-based pass */
+    int32_t member;   /* located member within the group, -1 if none */
+    int32_t action;   /* enum tfft_action */
+    int32_t method;   /* enum tfft_locate */
+    double residual;  /* |d1| = |R1 - L1| */
+    double threshold; /* tau */
+    double ratio_re, ratio_im; /* d2 / d1 */
+} tfft_record;
+
+/* Test instrument: one additive fault.  `value` (dre + i dim) is added to a
+ * register of the transform of signal `signal` in pass `pass`:
+ *   stage >= 0: to output `index` of butterfly stage `stage` (position in that
+ *               stage's output array, after the stage's butterflies);
+ *   stage == -1: to final output value `index` of the pass (after the
+ *               inter-pass twiddle, conjugation and scale), before the
+ *               post-transform checksum.
+ * For two-pass plans index = sub * pass_len + position, with sub the column
+ * (pass 0) or row (pass 1); for one-pass plans index = position.  This models
+ * a compute fault (paper Section II-A) inside the protected region. */
+typedef struct {
+    int64_t signal;
+    int32_t pass;
+    int32_t stage;
+    int64_t index;
+    double dre, dim;
+} tfft_fault;
+
+/* Create a plan for `batch` transforms of length `n` (a power of two,
+ * 2 <= n <= 2^24) of element type `dtype`.  Chooses one pass for n <= 4096 and
+ * two passes (n = n1 * n2, Section IV-A.1) above; generates every twiddle and
+ * checksum vector in binary64 on the host and rounds it once; allocates the
+ * tables, the workspace (two-pass plans: n * batch elements) and the report.
+ * *out receives the plan, or NULL on error.  E_INVALID for bad arguments,
+ * E_NOMEM / E_HIP on allocation failure. */
+int tfft_plan_create(tfft_plan *out, int64_t n, int64_t batch, int dtype, uint32_t flags);
+int tfft_plan_create_with(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_options *opt);
+
+/* Free a plan and everything it owns.  NULL is accepted. */
+int tfft_plan_destroy(tfft_plan p);
+
+/* Forward transform of the plan's batch, d_in -> d_out, on hip_stream.
+ * ft_mode is enum tfft_ft_mode.  Resets the report.  Returns E_INVALID for
+ * NULL, misaligned or overlapping buffers or a bad mode, E_HIP if a launch
+ * fails, else OK (the outcome of the checks is read with tfft_get_report). */
+int tfft_exec_forward(tfft_plan p, const void *d_in, void *d_out, int ft_mode, void *hip_stream);
+
+/* Inverse transform (w_N^{-jn}; times 1/N unless TFFT_INVERSE_UNSCALED). */
+int tfft_exec_inverse(tfft_plan p, const void *d_in, void *d_out, int ft_mode, void *hip_stream);
+
+/* Copy out the report of the last execution: counters into *counts (may be
+ * NULL) and up to `cap` records, sorted by (pass, group), into recs (may be
+ * NULL when cap == 0).  Synchronises the stream of the last execution.
+ * Returns UNCORRECTABLE if any flagged group was left uncorrected in CORRECT
+ * mode, E_STATE before the first execution, else OK. */
+int tfft_get_report(tfft_plan p, tfft_counts *counts, tfft_record *recs, int64_t cap);
+
+/* Test hook: install `n` fault specifications applied by every following
+ * execution (n = 0 clears them).  The specs are validated against the plan
+ * (signal, pass, stage and index in range) and copied; E_INVALID otherwise. */
+int tfft_set_faults(tfft_plan p, const tfft_fault *specs, int64_t n);
+
+/* Fill *info with the plan's decomposition and sizes. */
+int tfft_plan_info(tfft_plan p, tfft_plan_desc *info);
+
+/* Static text for a status code. */
+const char *tfft_status_string(int status);
+
+/* TFFT_VERSION of the library. */
+int tfft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TFFT_H */

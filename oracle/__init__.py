@@ -182,27 +182,37 @@ def encoding_vector(m: int) -> np.ndarray:
 def checksum_vector(m: int, inverse: bool = False, scale: float = 1.0) -> np.ndarray:
     """c = scale * (e^T W)^T for e = w_3^k, in closed form.
 
-    sum_k w_3^k a^k is geometric with ratio a = w_3 w_m^{+-n}; because
-    w_m^{n m} = 1 its sum is (1 - w_3^m) / (1 - w_3 w_m^{+-n}), never 0/0 for a
-    power-of-two m (m is not a multiple of 3)."""
+    e_k w_m^{+-k n} = w_{3m}^{k p} with p = (m +- 3 n) mod 3m, so c_n is the
+    geometric sum (1 - w_3^m) / (1 - w_{3m}^p) (w_{3m}^{p m} = w_3^m because
+    p = m mod 3; never 0/0 since m is a power of two, not a multiple of 3).
+    The denominator is evaluated without cancellation through the half angle:
+    1 - exp(-i phi) = 2 i sin(phi/2) exp(-i phi/2), phi = 2 pi p / 3m, with
+    exp(-i phi/2) = w_{6m}^p taken from the exactly reduced twiddle."""
     n = np.arange(m, dtype=np.int64)
-    wn = omega(n, m)
-    if inverse:
-        wn = np.conj(wn)
+    p = np.mod(m + (-3 if inverse else 3) * n, 3 * m)
+    w = omega(p, 6 * m)                       # exp(-i phi / 2)
     w3 = omega_table(3, 3)
-    w3m = w3[m % 3]
-    return scale * (1.0 - w3m) / (1.0 - w3[1] * wn)
+    num = 1.0 - w3[m % 3]
+    # 1 / (1 - exp(-i phi)) = conj(w) / (2 i sin(phi/2)) and sin(phi/2) = -Im(w)
+    return scale * num * np.conj(w) / (-2j * w.imag)
 
 
-def checksum_vector_direct(m: int, inverse: bool = False, scale: float = 1.0, e=None) -> np.ndarray:
-    """c_n = scale * sum_k e_k w_m^{+-k n}, summed term by term."""
+def checksum_vector_direct(m: int, inverse: bool = False, scale: float = 1.0, e=None, exact_sum=False) -> np.ndarray:
+    """c_n = scale * sum_k e_k w_m^{+-k n}, summed term by term (with
+    ``exact_sum`` each real and imaginary sum is math.fsum's correctly rounded
+    sum of the rounded terms)."""
     if e is None:
         e = encoding_vector(m)
     k = np.arange(m, dtype=np.int64)
     w = omega(np.outer(k, k) % m, m)
     if inverse:
         w = np.conj(w)
-    return scale * (e[:, None] * w).sum(axis=0)
+    terms = e[:, None] * w
+    if not exact_sum:
+        return scale * terms.sum(axis=0)
+    re = np.array([math.fsum(col) for col in terms.real.T])
+    im = np.array([math.fsum(col) for col in terms.imag.T])
+    return scale * (re + 1j * im)
 
 
 def threshold(m: int, s: float, kappa: float, u: float) -> float:
@@ -269,7 +279,8 @@ def two_sided_group(X, Yhat, *, inverse=False, scale=1.0, kappa=16.0, u=2.0 ** -
     Readings (the paper does not state them):
       * e = w_3^k (Wang) for the per-position vector; batch vectors w1 = 1,
         w2 = (1..G), one-based so that signal 0 is not weighted by zero;
-      * detection threshold: ``threshold``; the test !(|d1| <= tau) also flags NaN;
+      * detection threshold: ``threshold`` times |scale| (the rounding noise of
+        the outputs scales with them); the test !(|d1| <= tau) also flags NaN;
       * location j = round(Re(d2/d1)) - 1, accepted iff 0 <= j < G and
         |d2/d1 - (j+1)| <= 1/4; else, when enabled, the per-signal residuals
         e'_b . y_b - c . x_b locate the signal if exactly one exceeds its own
@@ -312,7 +323,7 @@ def two_sided_group(X, Yhat, *, inverse=False, scale=1.0, kappa=16.0, u=2.0 ** -
         R2 = complex(np.dot(w2, per_sig))
     d1, d2 = R1 - L1, R2 - L2
     S = float(np.sum(X.real ** 2 + X.imag ** 2))
-    tau = threshold(M, S, kappa, u)
+    tau = threshold(M, S, kappa, u) * abs(scale)
     flagged = not (abs(d1) <= tau)
     j, rho = _locate_by_quotient(d1, d2, G)
     rec = GroupRecord(group=group, flagged=flagged, d1=d1, d2=d2, tau=tau, s=S, rho=rho)
@@ -323,7 +334,7 @@ def two_sided_group(X, Yhat, *, inverse=False, scale=1.0, kappa=16.0, u=2.0 ** -
         with np.errstate(all="ignore"):
             db = per_sig - X @ c
             Sb = (X.real ** 2 + X.imag ** 2).sum(axis=1)
-            taub = np.array([threshold(M, float(sb), kappa, u) for sb in Sb])
+            taub = np.array([threshold(M, float(sb), kappa, u) * abs(scale) for sb in Sb])
             bad = np.flatnonzero(~(np.abs(db) <= taub))
         if bad.size == 1:
             j, method = int(bad[0]), "per-signal"

@@ -1,0 +1,223 @@
+"""Python binding of the fault-tolerant batched FFT library (``libtfft.so``).
+
+Argument marshalling only: every step of the transform and of the two-sided
+checksum runs in the HIP kernels behind the C ABI declared in
+``include/tfft.h``.  PyTorch supplies device memory and the HIP stream.
+There is no CPU fallback: if the library is not built, importing this package
+raises.
+
+The functions ``tfft_*`` mirror the C entry points one to one; ``Plan`` wraps
+them for torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import warnings
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtfft.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python -m paper_2405_02520_amd.build` (hipcc, gfx950) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ----------------------------------------------------------- ABI constants
+C64, C128 = 0, 1
+FT_OFF, FT_DETECT, FT_CORRECT = 0, 1, 2
+OK, UNCORRECTABLE = 0, 1
+E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_STATE = -1, -2, -3, -4, -5
+INVERSE_UNSCALED = 1
+ACT_DETECTED, ACT_CORRECTED, ACT_BENIGN, ACT_UNCORRECTABLE = 1, 2, 3, 4
+LOC_NONE, LOC_QUOTIENT, LOC_PER_SIGNAL = 0, 1, 2
+ACTION_NAMES = {ACT_DETECTED: "detected", ACT_CORRECTED: "corrected", ACT_BENIGN: "benign",
+                ACT_UNCORRECTABLE: "uncorrectable"}
+_MODES = {"off": FT_OFF, "detect": FT_DETECT, "correct": FT_CORRECT}
+
+
+class tfft_options(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("group", ctypes.c_int32), ("kappa", ctypes.c_double),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+class tfft_plan_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("batch", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("passes", ctypes.c_int32), ("pass_len", ctypes.c_int32 * 2), ("group", ctypes.c_int32 * 2),
+                ("elems_per_thread", ctypes.c_int32 * 2), ("tile_signals", ctypes.c_int32 * 2),
+                ("stages", ctypes.c_int32 * 2), ("radices", (ctypes.c_int32 * 8) * 2),
+                ("groups", ctypes.c_int64 * 2), ("workspace_bytes", ctypes.c_size_t), ("kappa", ctypes.c_double)]
+
+
+class tfft_counts(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("groups_checked", "detected", "corrected", "uncorrectable", "benign", "n_records", "dropped")]
+
+
+class tfft_record(ctypes.Structure):
+    _fields_ = [("signal", ctypes.c_int64), ("sub", ctypes.c_int64), ("group", ctypes.c_int64),
+                ("pass_", ctypes.c_int32), ("member", ctypes.c_int32), ("action", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("residual", ctypes.c_double), ("threshold", ctypes.c_double),
+                ("ratio_re", ctypes.c_double), ("ratio_im", ctypes.c_double)]
+
+
+class tfft_fault(ctypes.Structure):
+    _fields_ = [("signal", ctypes.c_int64), ("pass_", ctypes.c_int32), ("stage", ctypes.c_int32),
+                ("index", ctypes.c_int64), ("dre", ctypes.c_double), ("dim", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_sig = {
+    "tfft_plan_create": ([ctypes.POINTER(_P), ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32],
+                         ctypes.c_int),
+    "tfft_plan_create_with": ([ctypes.POINTER(_P), ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                               ctypes.POINTER(tfft_options)], ctypes.c_int),
+    "tfft_plan_destroy": ([_P], ctypes.c_int),
+    "tfft_exec_forward": ([_P, _P, _P, ctypes.c_int, _P], ctypes.c_int),
+    "tfft_exec_inverse": ([_P, _P, _P, ctypes.c_int, _P], ctypes.c_int),
+    "tfft_get_report": ([_P, ctypes.POINTER(tfft_counts), ctypes.POINTER(tfft_record), ctypes.c_int64],
+                        ctypes.c_int),
+    "tfft_set_faults": ([_P, ctypes.POINTER(tfft_fault), ctypes.c_int64], ctypes.c_int),
+    "tfft_plan_info": ([_P, ctypes.POINTER(tfft_plan_desc)], ctypes.c_int),
+    "tfft_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "tfft_version": ([], ctypes.c_int),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+    globals()[_name] = _f
+
+EXPORTED = tuple(_sig)
+
+
+class TfftError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {tfft_status_string(status).decode()} ({status})")
+        self.status = status
+
+
+def _check(status: int, what: str) -> int:
+    if status < 0:
+        raise TfftError(status, what)
+    return status
+
+
+@dataclass
+class Record:
+    signal: int
+    sub: int
+    group: int
+    pass_: int
+    member: int
+    action: str
+    method: int
+    residual: float
+    threshold: float
+    ratio: complex
+
+
+def _dtype_code(dtype) -> int:
+    s = str(dtype)
+    if s in ("c64", "complex64", "torch.complex64"):
+        return C64
+    if s in ("c128", "complex128", "torch.complex128"):
+        return C128
+    raise ValueError(f"unsupported dtype {dtype!r}")
+
+
+class Plan:
+    """A plan for ``batch`` length-``n`` complex transforms on the current device."""
+
+    def __init__(self, n: int, batch: int, dtype="c64", group: int = 0, kappa: float = 0.0,
+                 inverse_unscaled: bool = False):
+        self.n, self.batch = int(n), int(batch)
+        self.dtype_code = _dtype_code(dtype)
+        opt = tfft_options(flags=INVERSE_UNSCALED if inverse_unscaled else 0, group=int(group), kappa=float(kappa))
+        h = _P()
+        _check(tfft_plan_create_with(ctypes.byref(h), self.n, self.batch, self.dtype_code, ctypes.byref(opt)),
+               "tfft_plan_create_with")
+        self._h = h
+        self.last_status = OK
+
+    def close(self):
+        if getattr(self, "_h", None):
+            tfft_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        d = tfft_plan_desc()
+        _check(tfft_plan_info(self._h, ctypes.byref(d)), "tfft_plan_info")
+        p = d.passes
+        return dict(n=d.n, batch=d.batch, dtype=d.dtype, passes=p, pass_len=list(d.pass_len[:p]),
+                    group=list(d.group[:p]), elems_per_thread=list(d.elems_per_thread[:p]),
+                    tile_signals=list(d.tile_signals[:p]), stages=list(d.stages[:p]),
+                    radices=[list(d.radices[i][:d.stages[i]]) for i in range(p)], groups=list(d.groups[:p]),
+                    workspace_bytes=int(d.workspace_bytes), kappa=d.kappa)
+
+    def _check_tensor(self, t, name):
+        import torch
+        want = torch.complex64 if self.dtype_code == C64 else torch.complex128
+        if not t.is_cuda or t.dtype != want or not t.is_contiguous() or t.numel() != self.n * self.batch:
+            raise ValueError(f"{name} must be a contiguous {want} CUDA tensor with {self.batch}x{self.n} elements")
+
+    def _exec(self, fn, x, out, ft_mode, stream):
+        import torch
+        self._check_tensor(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_tensor(out, "output")
+        mode = _MODES[ft_mode] if isinstance(ft_mode, str) else int(ft_mode)
+        st = stream if stream is not None else torch.cuda.current_stream(x.device)
+        _check(fn(self._h, x.data_ptr(), out.data_ptr(), mode, st.cuda_stream), fn.__name__)
+        return out
+
+    def forward(self, x, out=None, ft_mode="correct", stream=None):
+        return self._exec(tfft_exec_forward, x, out, ft_mode, stream)
+
+    def inverse(self, x, out=None, ft_mode="correct", stream=None):
+        return self._exec(tfft_exec_inverse, x, out, ft_mode, stream)
+
+    def set_faults(self, faults):
+        """faults: iterable of dicts with keys signal, pass_, stage, index, value (complex)."""
+        faults = list(faults)
+        arr = (tfft_fault * max(1, len(faults)))()
+        for i, f in enumerate(faults):
+            v = complex(f.get("value", 0.0))
+            arr[i] = tfft_fault(int(f["signal"]), int(f.get("pass_", 0)), int(f.get("stage", -1)),
+                                int(f["index"]), v.real, v.imag)
+        _check(tfft_set_faults(self._h, arr, len(faults)), "tfft_set_faults")
+
+    def report(self, cap: int | None = None):
+        """(counts dict, [Record]) of the last execution; synchronises its stream."""
+        counts = tfft_counts()
+        st = tfft_get_report(self._h, ctypes.byref(counts), None, 0)
+        _check(st, "tfft_get_report")
+        n = counts.n_records if cap is None else min(cap, counts.n_records)
+        recs = (tfft_record * max(1, n))()
+        st = _check(tfft_get_report(self._h, ctypes.byref(counts), recs, n), "tfft_get_report")
+        self.last_status = st
+        if st == UNCORRECTABLE:
+            warnings.warn("tfft: a flagged checksum group could not be corrected", RuntimeWarning, stacklevel=2)
+        c = {k: getattr(counts, k) for k, _ in tfft_counts._fields_}
+        out = [Record(r.signal, r.sub, r.group, r.pass_, r.member, ACTION_NAMES.get(r.action, str(r.action)),
+                      r.method, r.residual, r.threshold, complex(r.ratio_re, r.ratio_im)) for r in recs[:n]]
+        return c, out

@@ -1,0 +1,106 @@
+// Internal definitions shared by the host plan code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tfft {
+
+// Pass roles of the tiled FFT (TurboFFT Section IV-A.1).
+//  ROWS   one-pass plan: each signal is contiguous, output contiguous.
+//  COLS   first pass of a two-pass plan: length-n1 columns (stride n2) of each
+//         signal, multiplied by the inter-pass twiddle w_N^{k1 n2}, stored
+//         back in the same [n1][n2] layout into the workspace.
+//  ROWS_T second pass: length-n2 rows of the workspace, stored transposed,
+//         y[k1 + n1 k2].
+enum Kind { KIND_ROWS = 0, KIND_COLS = 1, KIND_ROWS_T = 2 };
+
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+constexpr int ipowc(int b, int e) { return e == 0 ? 1 : b * ipowc(b, e - 1); }
+
+// ---------------------------------------------------------------- config
+// Elements held by one thread (the thread-level radix, Section IV-A.2).
+constexpr int cfg_E(int fp64, int M) { return M >= 8 ? 8 : M; }
+// Signals held in LDS at once by one workgroup (the tile).  A tile has at
+// most 256 threads (more only when one signal alone needs more) and at most
+// 64 KiB of LDS.
+constexpr int cfg_C(int fp64, int M, int kind) {
+    const int E = cfg_E(fp64, M);
+    const int T = M / E;
+    const int S = fp64 ? 16 : 8;
+    int c = kind == KIND_ROWS ? 256 / (T > 0 ? T : 1) : 16;
+    if (c > 16) c = 16;
+    while (c > 1 && (c * T > 256 || c * M * S > 65536)) c /= 2;
+    return c < 1 ? 1 : c;
+}
+// Keep the stage twiddles / the checksum vector of a thread in registers
+// across the signals it processes (1), or re-read them from the L1/L2
+// resident tables for every signal (0).
+constexpr int cfg_twreg(int fp64, int M, int kind) { return 0; }
+constexpr int cfg_creg(int fp64, int M, int kind) { return 0; }
+constexpr int cfg_threads(int fp64, int M, int kind) { return cfg_C(fp64, M, kind) * (M / cfg_E(fp64, M)); }
+
+// Radix sequence: as many stages of radix E as fit, then one stage of the
+// remaining factor (which divides E).
+constexpr int n_full(int M, int E) { return E <= 1 ? 0 : ilog2c(M) / ilog2c(E); }
+constexpr int n_stages(int M, int E) { return ipowc(E, n_full(M, E)) == M ? n_full(M, E) : n_full(M, E) + 1; }
+constexpr int stage_radix(int M, int E, int s) { return s < n_full(M, E) ? E : M / ipowc(E, n_full(M, E)); }
+constexpr int stage_ns(int M, int E, int s) { return s <= n_full(M, E) ? ipowc(E, s) : M; }
+
+// ---------------------------------------------------------------- report
+struct DevRecord {
+    int64_t group;
+    int32_t pass, action, member, method;
+    double d1r, d1i, d2r, d2i, tau, s;
+};
+
+struct DevReport {
+    unsigned long long n_flag;         // flagged groups (record slots requested)
+    unsigned long long corrected, benign, uncorrectable;
+};
+
+// One fault, resolved by the host to the register that holds the element.
+struct DevFault {
+    int64_t group;   // group within the pass
+    int32_t member;  // member within the group
+    int32_t stage;   // butterfly stage, -1 = final value
+    int32_t j, m;    // thread within the signal, register index
+    int32_t next;    // next fault of the same group, -1 = end
+    int32_t pad_;
+    double dre, dim;
+};
+
+// Geometry and tables of one pass launch.
+struct PassArgs {
+    const void *in;
+    void *out;
+    int64_t batch;      // B
+    int64_t n;          // full transform length N
+    int32_t n1, n2;     // two-pass split N = n1 * n2 (one-pass: n1 = N, n2 = 1)
+    int32_t G;          // members per checksum group
+    int32_t rb;         // two-pass: batch entries per group (G = C * rb)
+    int64_t n_strips;   // two-pass: tiles of C sub-signals per batch entry
+    int64_t n_groups;   // groups of this launch
+    int32_t conj_in, conj_out;
+    double out_scale;   // applied to the final values when != 1
+    const double *cvec; // [2M] checksum vector c of this pass and direction (fp64)
+    const void *stw;    // [2M] stage twiddles w_M^t in the element type
+    const double *stw64;// [2M] the same in fp64 (correction path)
+    const double *itw_lo, *itw_hi; // w_N^t = lo[t & (2^bits - 1)] * hi[t >> bits]
+    int32_t itw_bits;
+    int32_t pass;
+    double tau_coef;    // tau = tau_coef * sqrt(S)
+    DevReport *rep;
+    DevRecord *recs;
+    int64_t rec_cap;
+    const int32_t *fault_head; // [n_groups] first fault of each group or -1; NULL if none
+    const DevFault *faults;
+};
+
+// Host-side launchers (defined in the kernel translation unit).
+hipError_t launch_pass(int fp64, int M, int kind, int ft, const PassArgs &a, int grid, hipStream_t st);
+hipError_t launch_correct(int fp64, int M, int kind, const PassArgs &a, int grid, hipStream_t st);
+hipError_t launch_reset(DevReport *rep, hipStream_t st);
+int pass_max_grid(int fp64, int M, int kind, int ft);
+
+}  // namespace tfft

@@ -1,0 +1,728 @@
+// HIP kernels of the fault-tolerant batched FFT for CDNA4 (gfx950).
+//
+// One launch per pass of the tiled FFT (TurboFFT Section IV-A.1).  A
+// workgroup owns one checksum group at a time (Section IV-B.2, the
+// threadblock-level two-sided checksum) and walks its members a tile of C
+// signals at a time:
+//   load   coalesced global loads into registers; in the same registers the
+//          pre-transform checksum c . x (fp64) is accumulated, weighted by 1
+//          and by the member's one-based index (Section III, Eq. (4)-(5));
+//   stages Stockham radix-E butterflies held in registers (the thread-level
+//          macro FFT, Section IV-A.2) with LDS transposes between stages;
+//          stage twiddles come from an fp64-generated table rounded once;
+//   store  post-transform checksum e . y in fp64 on the final registers, then
+//          coalesced stores;
+//   check  one workgroup reduction per group; a residual beyond tau is
+//          recorded with the residual quotient that locates the member.
+// Flagged groups are corrected afterwards by a separate launch (delayed,
+// batched correction, Section III-B) that rebuilds the located member from
+// the transform of the group's combined input, in fp64.
+#include <type_traits>
+#include <utility>
+
+#include "tfft_internal.h"
+
+namespace tfft {
+
+// ------------------------------------------------------------- complex
+template <typename R>
+struct cx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> cadd(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> csub(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> cmulconj(cx<R> a, cx<R> b) {  // a * conj(b)
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+
+template <typename R>
+struct vec2;
+template <>
+struct vec2<float> { using type = float2; };
+template <>
+struct vec2<double> { using type = double2; };
+
+template <typename R>
+__device__ __forceinline__ cx<R> ldg(const cx<R> *p) {
+    typename vec2<R>::type v = *reinterpret_cast<const typename vec2<R>::type *>(p);
+    return {v.x, v.y};
+}
+template <typename R>
+__device__ __forceinline__ void stg(cx<R> *p, cx<R> a) {
+    typename vec2<R>::type v;
+    v.x = a.re;
+    v.y = a.im;
+    *reinterpret_cast<typename vec2<R>::type *>(p) = v;
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// ---------------------------------------------------- small DFT in registers
+// Multiply by w_LEN^K = exp(-2 pi i K / LEN) for compile-time K < LEN/2,
+// LEN <= 16; trivial factors cost no multiplication.
+constexpr double kSqrtHalf = 0.70710678118654752440;
+constexpr double kCos1_16 = 0.92387953251128675613;  // cos(pi/8)
+constexpr double kSin1_16 = 0.38268343236508977173;  // sin(pi/8)
+
+template <typename R, int K, int LEN>
+__device__ __forceinline__ cx<R> mul_wconst(cx<R> x) {
+    constexpr int idx = (K * 16) / LEN;  // angle = 2 pi idx / 16
+    if constexpr (idx == 0) {
+        return x;
+    } else if constexpr (idx == 4) {
+        return {x.im, -x.re};
+    } else if constexpr (idx == 2) {
+        const R h = R(kSqrtHalf);
+        return {h * (x.re + x.im), h * (x.im - x.re)};
+    } else if constexpr (idx == 6) {
+        const R h = R(kSqrtHalf);
+        return {h * (x.im - x.re), -h * (x.re + x.im)};
+    } else {
+        constexpr double c = idx == 1 ? kCos1_16 : idx == 3 ? kSin1_16 : idx == 5 ? -kSin1_16 : -kCos1_16;
+        constexpr double s = idx == 1 ? kSin1_16 : idx == 3 ? kCos1_16 : idx == 5 ? kCos1_16 : kSin1_16;
+        return {x.re * R(c) + x.im * R(s), x.im * R(c) - x.re * R(s)};
+    }
+}
+
+constexpr int bitrev_c(int v, int bits) { return bits == 0 ? 0 : ((v & 1) << (bits - 1)) | bitrev_c(v >> 1, bits - 1); }
+
+// In-place length-RAD DFT (forward) of v[0..RAD): iterative radix-2
+// decimation in time on bit-reversed registers, natural-order output.
+template <typename R, int RAD>
+__device__ __forceinline__ void dft_small(cx<R> *v) {
+    if constexpr (RAD > 1) {
+        constexpr int BITS = ilog2c(RAD);
+        cx<R> a[RAD];
+        static_for<0, RAD>([&](auto i) { a[i] = v[bitrev_c(i, BITS)]; });
+        static_for<1, BITS + 1>([&](auto L) {
+            constexpr int LEN = 1 << L;
+            static_for<0, RAD / LEN>([&](auto blk) {
+                static_for<0, LEN / 2>([&](auto k) {
+                    constexpr int i0 = blk * LEN + k;
+                    constexpr int i1 = i0 + LEN / 2;
+                    const cx<R> t = mul_wconst<R, k, LEN>(a[i1]);
+                    const cx<R> u = a[i0];
+                    a[i0] = cadd(u, t);
+                    a[i1] = csub(u, t);
+                });
+            });
+        });
+        static_for<0, RAD>([&](auto i) { v[i] = a[i]; });
+    }
+}
+
+// ------------------------------------------------------ per-stage constants
+template <int M, int E>
+struct Stages {
+    static constexpr int count = n_stages(M, E);
+    static constexpr int T = M / E;
+    static constexpr int radix(int s) { return stage_radix(M, E, s); }
+    static constexpr int ns(int s) { return stage_ns(M, E, s); }
+    static constexpr int nb(int s) { return E / stage_radix(M, E, s); }
+    // twiddle registers of stages 1..s-1
+    static constexpr int tw_off(int s) { return s <= 1 ? 0 : tw_off(s - 1) + nb(s - 1) * (radix(s - 1) - 1); }
+    static constexpr int tw_count() { return tw_off(count) > 0 ? tw_off(count) : 1; }
+};
+
+// ----------------------------------------------------------- addressing
+struct MemberLoc {
+    int64_t in_off, in_stride, out_off, out_stride, sub;
+    bool valid;
+};
+
+template <int M, int KIND, int C>
+__device__ __forceinline__ MemberLoc member_loc(const PassArgs &a, int64_t g, int b) {
+    MemberLoc L;
+    if constexpr (KIND == KIND_ROWS) {
+        const int64_t s = g * a.G + b;
+        L.valid = s < a.batch;
+        L.in_off = s * M;
+        L.in_stride = 1;
+        L.out_off = s * M;
+        L.out_stride = 1;
+        L.sub = 0;
+    } else {
+        const int64_t strip = g % a.n_strips;
+        const int64_t beta = (g / a.n_strips) * a.rb + b / C;
+        const int64_t sub = strip * C + b % C;
+        L.valid = beta < a.batch;
+        L.sub = sub;
+        if constexpr (KIND == KIND_COLS) {
+            L.in_off = beta * a.n + sub;
+            L.in_stride = a.n2;
+            L.out_off = L.in_off;
+            L.out_stride = a.n2;
+        } else {
+            L.in_off = beta * a.n + sub * a.n2;
+            L.in_stride = 1;
+            L.out_off = beta * a.n + sub;
+            L.out_stride = a.n1;
+        }
+    }
+    return L;
+}
+
+// w_N^t from the two-level fp64 table.
+__device__ __forceinline__ cx<double> itw(const PassArgs &a, int64_t t) {
+    const int64_t mask = (int64_t(1) << a.itw_bits) - 1;
+    const cx<double> lo = ldg(reinterpret_cast<const cx<double> *>(a.itw_lo) + (t & mask));
+    const cx<double> hi = ldg(reinterpret_cast<const cx<double> *>(a.itw_hi) + (t >> a.itw_bits));
+    return cmul(lo, hi);
+}
+
+template <typename R, int E>
+__device__ __noinline__ void apply_faults(cx<R> (&d)[E], const DevFault *F, int fh, int stage, int b, int j) {
+    for (int f = fh; f >= 0; f = F[f].next) {
+        const DevFault x = F[f];
+        if (x.stage == stage && x.member == b && x.j == j) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                if (m == x.m) {
+                    d[m].re += R(x.dre);
+                    d[m].im += R(x.dim);
+                }
+            }
+        }
+    }
+}
+
+constexpr double kW3r = -0.5;
+constexpr double kW3i = -0.86602540378443864676;  // w_3 = exp(-2 pi i / 3)
+
+__device__ __forceinline__ double wave_sum(double v, int width) {
+    for (int off = width / 2; off > 0; off /= 2) v += __shfl_xor(v, off, width);
+    return v;
+}
+
+// ------------------------------------------------------------- pass kernel
+template <typename R, int M, int KIND, bool FT>
+__global__ void __launch_bounds__(cfg_threads(sizeof(R) == 8, M, KIND))
+pass_kernel(PassArgs a) {
+    constexpr int FP64 = sizeof(R) == 8;
+    constexpr int E = cfg_E(FP64, M);
+    constexpr int T = M / E;
+    constexpr int C = cfg_C(FP64, M, KIND);
+    constexpr int NT = C * T;
+    using St = Stages<M, E>;
+    constexpr int NSTAGE = St::count;
+    constexpr int WAVES = (NT + 63) / 64;
+    constexpr int WIDTH = NT < 64 ? NT : 64;
+
+    __shared__ cx<R> lds[C * M];
+    __shared__ double red[WAVES][5];
+
+    const int tid = threadIdx.x;
+    int c, j;
+    if constexpr (KIND == KIND_COLS) {
+        c = tid % C;
+        j = tid / C;
+    } else {
+        c = tid / T;
+        j = tid % T;
+    }
+    const cx<R> *in = reinterpret_cast<const cx<R> *>(a.in);
+    cx<R> *out = reinterpret_cast<cx<R> *>(a.out);
+
+    // LDS index of element `pos` of tile slot `slot`
+    auto lidx = [](int slot, int pos) -> int {
+        if constexpr (KIND == KIND_COLS) return pos * C + slot;
+        else return slot * M + pos;
+    };
+
+    // Stage twiddles w_{NS*RAD}^{(i mod NS) q} (from the table of w_M^t) and
+    // the pre-transform checksum vector at positions j + T m: either kept in
+    // registers for all signals of the workgroup or re-read per signal.
+    constexpr bool TWREG = cfg_twreg(FP64, M, KIND) != 0;
+    constexpr bool CREG = FT && cfg_creg(FP64, M, KIND) != 0;
+    const cx<R> *stw = reinterpret_cast<const cx<R> *>(a.stw);
+    const cx<double> *cv = reinterpret_cast<const cx<double> *>(a.cvec);
+    auto stage_tw = [&](auto S, auto p, auto q) -> cx<R> {
+        constexpr int s = S;
+        constexpr int RAD = St::radix(s), NS = St::ns(s);
+        const int i = j + p * T;
+        return ldg(stw + ((i % NS) * q) * (M / (NS * RAD)));
+    };
+    cx<R> tw[TWREG ? St::tw_count() : 1];
+    if constexpr (TWREG) {
+        static_for<1, NSTAGE>([&](auto S) {
+            constexpr int s = S;
+            constexpr int RAD = St::radix(s), NB = St::nb(s);
+            static_for<0, NB>([&](auto p) {
+                static_for<1, RAD>([&](auto q) { tw[St::tw_off(s) + p * (RAD - 1) + (q - 1)] = stage_tw(S, p, q); });
+            });
+        });
+    }
+    cx<double> cc[CREG ? E : 1];
+    if constexpr (CREG) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) cc[m] = ldg(cv + j + T * m);
+    }
+    // e_k = w_3^(k mod 3) with k = j + T m: class of register m, rotated by j
+    const int jr = j % 3;
+    const double rotr = jr == 0 ? 1.0 : kW3r;
+    const double roti = jr == 0 ? 0.0 : (jr == 1 ? kW3i : -kW3i);
+
+    const int nwg = gridDim.x;
+    int64_t wl = blockIdx.x;
+    if (nwg % 8 == 0) wl = (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;  // XCD-contiguous group ranges
+
+    const int rounds = a.G / C;
+    for (int64_t g = wl; g < a.n_groups; g += nwg) {
+        const int fh = a.fault_head ? a.fault_head[g] : -1;
+        double D1r = 0.0, D1i = 0.0, D2r = 0.0, D2i = 0.0, Ssum = 0.0;
+        for (int r = 0; r < rounds; ++r) {
+            const int b = r * C + c;
+            const MemberLoc L = member_loc<M, KIND, C>(a, g, b);
+            cx<R> d[E];
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                d[m] = cx<R>{R(0), R(0)};
+                if (L.valid) d[m] = ldg(in + L.in_off + (int64_t)(j + T * m) * L.in_stride);
+            }
+            if constexpr (FT) {
+                double lr = 0.0, li = 0.0;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const double xr = double(d[m].re), xi = double(d[m].im);
+                    cx<double> cm;
+                    if constexpr (CREG) cm = cc[m];
+                    else cm = ldg(cv + j + T * m);
+                    lr += cm.re * xr - cm.im * xi;
+                    li += cm.re * xi + cm.im * xr;
+                    Ssum += xr * xr + xi * xi;
+                }
+                const double w2 = double(b + 1);
+                D1r -= lr;
+                D1i -= li;
+                D2r -= w2 * lr;
+                D2i -= w2 * li;
+            }
+            if (a.conj_in) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) d[m].im = -d[m].im;
+            }
+
+            static_for<0, NSTAGE>([&](auto S) {
+                constexpr int s = S;
+                constexpr int RAD = St::radix(s), NS = St::ns(s), NB = St::nb(s);
+                if constexpr (s > 0) {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) d[m] = lds[lidx(c, j + T * m)];
+                    __syncthreads();
+                    static_for<0, NB>([&](auto p) {
+                        static_for<1, RAD>([&](auto q) {
+                            cx<R> w;
+                            if constexpr (TWREG) w = tw[St::tw_off(s) + p * (RAD - 1) + (q - 1)];
+                            else w = stage_tw(S, p, q);
+                            d[p + q * NB] = cmul(d[p + q * NB], w);
+                        });
+                    });
+                }
+                static_for<0, NB>([&](auto p) {
+                    cx<R> v[RAD];
+                    static_for<0, RAD>([&](auto q) { v[q] = d[p + q * NB]; });
+                    dft_small<R, RAD>(v);
+                    static_for<0, RAD>([&](auto q) { d[p + q * NB] = v[q]; });
+                });
+                if (fh >= 0) apply_faults<R, E>(d, a.faults, fh, s, b, j);
+                if constexpr (s < NSTAGE - 1) {
+                    static_for<0, NB>([&](auto p) {
+                        const int i = j + p * T;
+                        const int base = (i / NS) * NS * RAD + (i % NS);
+                        static_for<0, RAD>([&](auto q) { lds[lidx(c, base + q * NS)] = d[p + q * NB]; });
+                    });
+                    __syncthreads();
+                }
+            });
+
+            // final values: register m holds output position k = j + T m
+            // inter-pass twiddle (COLS): w_N^{k sub} = A B^m with A = w_N^{j sub},
+            // B = w_N^{T sub}, products in fp64, each rounded once
+            cx<double> twA{1.0, 0.0}, twB{1.0, 0.0};
+            if constexpr (KIND == KIND_COLS) {
+                twA = itw(a, (int64_t(j) * L.sub) % a.n);
+                twB = itw(a, (int64_t(T) * L.sub) % a.n);
+                cx<double> P = twA;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    d[m] = cmul(d[m], cx<R>{R(P.re), R(P.im)});
+                    if (m + 1 < E) P = cmul(P, twB);
+                }
+            }
+            if (a.conj_out) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) d[m].im = -d[m].im;
+            }
+            if (a.out_scale != 1.0) {
+                const R sc = R(a.out_scale);
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    d[m].re *= sc;
+                    d[m].im *= sc;
+                }
+            }
+            if (fh >= 0) apply_faults<R, E>(d, a.faults, fh, -1, b, j);
+            if constexpr (FT) {
+                double Ar[3] = {0.0, 0.0, 0.0}, Ai[3] = {0.0, 0.0, 0.0};
+                cx<double> P = twA;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int cls = ((T % 3) * m) % 3;
+                    double vr = double(d[m].re), vi = double(d[m].im);
+                    if constexpr (KIND == KIND_COLS) {
+                        // e' = e conj(applied twiddle); applied = P (forward) or conj(P) (inverse)
+                        const double pr = P.re, pi = a.conj_out ? -P.im : P.im;
+                        const double ur = vr * pr + vi * pi, ui = vi * pr - vr * pi;
+                        vr = ur;
+                        vi = ui;
+                        if (m + 1 < E) P = cmul(P, twB);
+                    }
+                    Ar[cls] += vr;
+                    Ai[cls] += vi;
+                }
+                // sum_c w_3^c A_c, then rotate by w_3^(j mod 3)
+                const double sr = Ar[0] + kW3r * (Ar[1] + Ar[2]) - kW3i * (Ai[1] - Ai[2]);
+                const double si = Ai[0] + kW3r * (Ai[1] + Ai[2]) + kW3i * (Ar[1] - Ar[2]);
+                const double rr = sr * rotr - si * roti, ri = sr * roti + si * rotr;
+                const double w2 = double(b + 1);
+                D1r += rr;
+                D1i += ri;
+                D2r += w2 * rr;
+                D2i += w2 * ri;
+            }
+            if constexpr (KIND == KIND_ROWS_T) {
+                // transposed store: re-map through LDS so that lanes run along
+                // the C adjacent rows of the tile
+#pragma unroll
+                for (int m = 0; m < E; ++m) lds[c * M + j + T * m] = d[m];
+                __syncthreads();
+                const int c2 = tid % C, j2 = tid / C;
+                const int64_t base = L.out_off - c + c2;  // rows of one tile share beta
+                if (L.valid) {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) stg(out + base + (int64_t)(j2 + T * m) * a.n1, lds[c2 * M + j2 + T * m]);
+                }
+                __syncthreads();
+            } else {
+                if (L.valid) {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) stg(out + L.out_off + (int64_t)(j + T * m) * L.out_stride, d[m]);
+                }
+            }
+        }  // rounds
+
+        if constexpr (FT) {
+            double v[5] = {D1r, D1i, D2r, D2i, Ssum};
+#pragma unroll
+            for (int k = 0; k < 5; ++k) v[k] = wave_sum(v[k], WIDTH);
+            if ((tid & 63) == 0) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) red[tid >> 6][k] = v[k];
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double t[5] = {0, 0, 0, 0, 0};
+                for (int w = 0; w < WAVES; ++w)
+                    for (int k = 0; k < 5; ++k) t[k] += red[w][k];
+                const double d1r = t[0], d1i = t[1], d2r = t[2], d2i = t[3], S = t[4];
+                const double tau = a.tau_coef * sqrt(S);
+                const double ad1 = sqrt(d1r * d1r + d1i * d1i);
+                if (!(ad1 <= tau)) {
+                    const double den = d1r * d1r + d1i * d1i;
+                    const double rhor = (d2r * d1r + d2i * d1i) / den;
+                    const double rhoi = (d2i * d1r - d2r * d1i) / den;
+                    int jl = -1;
+                    if (isfinite(rhor) && isfinite(rhoi)) {
+                        const double fj = floor(rhor + 0.5);
+                        if (fj >= 1.0 && fj <= double(a.G)) {
+                            const double er = rhor - fj;
+                            if (sqrt(er * er + rhoi * rhoi) <= 0.25) jl = int(fj) - 1;
+                        }
+                    }
+                    const unsigned long long slot = atomicAdd(&a.rep->n_flag, 1ULL);
+                    if ((int64_t)slot < a.rec_cap) {
+                        DevRecord rc;
+                        rc.group = g;
+                        rc.pass = a.pass;
+                        rc.action = 1;  // detected
+                        rc.member = jl;
+                        rc.method = jl >= 0 ? 1 : 0;
+                        rc.d1r = d1r;
+                        rc.d1i = d1i;
+                        rc.d2r = d2r;
+                        rc.d2i = d2i;
+                        rc.tau = tau;
+                        rc.s = S;
+                        a.recs[slot] = rc;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }  // groups
+}
+
+// ------------------------------------------------------- correction kernel
+constexpr int kCorrThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double *scratch) {
+    v = wave_sum(v, 64);
+    const int tid = threadIdx.x;
+    __syncthreads();
+    if ((tid & 63) == 0) scratch[tid >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kCorrThreads / 64; ++w) t += scratch[w];
+    return t;
+}
+
+template <typename R, int M, int KIND>
+__global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
+    constexpr int FP64 = sizeof(R) == 8;
+    constexpr int C = cfg_C(FP64, M, KIND);
+    __shared__ cx<double> buf[2][M];
+    __shared__ double scratch[kCorrThreads / 64];
+    const int tid = threadIdx.x;
+    const cx<R> *in = reinterpret_cast<const cx<R> *>(a.in);
+    cx<R> *out = reinterpret_cast<cx<R> *>(a.out);
+    const cx<double> *cv = reinterpret_cast<const cx<double> *>(a.cvec);
+    const cx<double> *w64 = reinterpret_cast<const cx<double> *>(a.stw64);
+
+    unsigned long long nrec = a.rep->n_flag;
+    if ((int64_t)nrec > a.rec_cap) nrec = a.rec_cap;
+    for (int64_t i = blockIdx.x; i < (int64_t)nrec; i += gridDim.x) {
+        const DevRecord rec = a.recs[i];
+        if (rec.pass != a.pass || rec.action != 1) continue;
+        const int64_t g = rec.group;
+
+        // applied output twiddle of member loc at output k (1 outside COLS)
+        auto applied = [&](const MemberLoc &L, int k) -> cx<double> {
+            if constexpr (KIND == KIND_COLS) {
+                cx<double> w = itw(a, (int64_t(k) * L.sub) % a.n);
+                if (a.conj_out) w.im = -w.im;
+                return w;
+            } else {
+                return cx<double>{1.0, 0.0};
+            }
+        };
+        auto load_in = [&](const MemberLoc &L, int n) -> cx<double> {
+            const cx<R> x = ldg(in + L.in_off + (int64_t)n * L.in_stride);
+            return {double(x.re), double(x.im)};
+        };
+        auto load_out = [&](const MemberLoc &L, int k) -> cx<double> {
+            const cx<R> y = ldg(out + L.out_off + (int64_t)k * L.out_stride);
+            return {double(y.re), double(y.im)};
+        };
+        auto ek = [](int k) -> cx<double> {
+            const int r = k % 3;
+            return {r == 0 ? 1.0 : kW3r, r == 0 ? 0.0 : (r == 1 ? kW3i : -kW3i)};
+        };
+
+        // location: quotient of the residuals, else per-signal residuals
+        int jl = rec.member;
+        int method = jl >= 0 ? 1 : 0;
+        if (jl < 0) {
+            int ncand = 0, cand = -1;
+            for (int b = 0; b < a.G; ++b) {
+                const MemberLoc L = member_loc<M, KIND, C>(a, g, b);
+                if (!L.valid) continue;
+                double dr = 0.0, di = 0.0, sb = 0.0;
+                for (int n = tid; n < M; n += kCorrThreads) {
+                    const cx<double> x = load_in(L, n);
+                    const cx<double> cn = cv[n];
+                    dr -= cn.re * x.re - cn.im * x.im;
+                    di -= cn.re * x.im + cn.im * x.re;
+                    sb += x.re * x.re + x.im * x.im;
+                    const cx<double> y = cmulconj(load_out(L, n), applied(L, n));
+                    const cx<double> e = ek(n);
+                    dr += e.re * y.re - e.im * y.im;
+                    di += e.re * y.im + e.im * y.re;
+                }
+                dr = block_sum(dr, scratch);
+                di = block_sum(di, scratch);
+                sb = block_sum(sb, scratch);
+                const double taub = a.tau_coef * sqrt(sb);
+                if (!(sqrt(dr * dr + di * di) <= taub)) {
+                    ++ncand;
+                    cand = b;
+                }
+            }
+            if (ncand == 1) {
+                jl = cand;
+                method = 2;
+            }
+        }
+
+        // transform of the combined input, fp64, Stockham radix-2 in LDS
+        for (int n = tid; n < M; n += kCorrThreads) {
+            cx<double> acc{0.0, 0.0};
+            for (int b = 0; b < a.G; ++b) {
+                const MemberLoc L = member_loc<M, KIND, C>(a, g, b);
+                if (L.valid) acc = cadd(acc, load_in(L, n));
+            }
+            if (a.conj_in) acc.im = -acc.im;
+            buf[0][n] = acc;
+        }
+        __syncthreads();
+        int src = 0;
+        for (int ns = 1; ns < M; ns *= 2) {
+            for (int t = tid; t < M / 2; t += kCorrThreads) {
+                const int k = t & (ns - 1);
+                const cx<double> w = w64[k * (M / (2 * ns))];
+                const cx<double> x0 = buf[src][t];
+                const cx<double> x1 = cmul(buf[src][t + M / 2], w);
+                const int o = (t / ns) * 2 * ns + k;
+                buf[src ^ 1][o] = cadd(x0, x1);
+                buf[src ^ 1][o + ns] = csub(x0, x1);
+            }
+            __syncthreads();
+            src ^= 1;
+        }
+        for (int k = tid; k < M; k += kCorrThreads) {
+            cx<double> p = buf[src][k];
+            if (a.conj_out) p.im = -p.im;
+            p.re *= a.out_scale;
+            p.im *= a.out_scale;
+            buf[src][k] = p;
+        }
+        __syncthreads();
+
+        int action;
+        if (jl >= 0) {
+            const MemberLoc Lj = member_loc<M, KIND, C>(a, g, jl);
+            for (int k = tid; k < M; k += kCorrThreads) {
+                cx<double> acc = buf[src][k];
+                for (int b = 0; b < a.G; ++b) {
+                    if (b == jl) continue;
+                    const MemberLoc L = member_loc<M, KIND, C>(a, g, b);
+                    if (L.valid) acc = csub(acc, cmulconj(load_out(L, k), applied(L, k)));
+                }
+                const cx<double> y = cmul(acc, applied(Lj, k));
+                stg(out + Lj.out_off + (int64_t)k * Lj.out_stride, cx<R>{R(y.re), R(y.im)});
+            }
+            action = 2;
+        } else {
+            double nrm = 0.0;
+            for (int k = tid; k < M; k += kCorrThreads) {
+                cx<double> acc = buf[src][k];
+                for (int b = 0; b < a.G; ++b) {
+                    const MemberLoc L = member_loc<M, KIND, C>(a, g, b);
+                    if (L.valid) acc = csub(acc, cmulconj(load_out(L, k), applied(L, k)));
+                }
+                nrm += acc.re * acc.re + acc.im * acc.im;
+            }
+            nrm = block_sum(nrm, scratch);
+            action = (sqrt(nrm) <= rec.tau) ? 3 : 4;
+        }
+        if (tid == 0) {
+            a.recs[i].member = jl;
+            a.recs[i].method = method;
+            a.recs[i].action = action;
+            atomicAdd(action == 2 ? &a.rep->corrected : action == 3 ? &a.rep->benign : &a.rep->uncorrectable, 1ULL);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void reset_kernel(DevReport *rep) {
+    if (threadIdx.x == 0) {
+        rep->n_flag = 0;
+        rep->corrected = 0;
+        rep->benign = 0;
+        rep->uncorrectable = 0;
+    }
+}
+
+// ------------------------------------------------------------- dispatch
+template <typename R, int M, int KIND, bool FT>
+static hipError_t launch_one(const PassArgs &a, int grid, hipStream_t st) {
+    constexpr int NT = cfg_threads(sizeof(R) == 8, M, KIND);
+    hipLaunchKernelGGL((pass_kernel<R, M, KIND, FT>), dim3(grid), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename R, int M, int KIND>
+static hipError_t launch_kind(int ft, const PassArgs &a, int grid, hipStream_t st) {
+    return ft ? launch_one<R, M, KIND, true>(a, grid, st) : launch_one<R, M, KIND, false>(a, grid, st);
+}
+
+template <typename R, int M>
+static hipError_t launch_m(int kind, int ft, const PassArgs &a, int grid, hipStream_t st) {
+    if (kind == KIND_ROWS) return launch_kind<R, M, KIND_ROWS>(ft, a, grid, st);
+    if constexpr (M >= 64) {
+        if (kind == KIND_COLS) return launch_kind<R, M, KIND_COLS>(ft, a, grid, st);
+        if (kind == KIND_ROWS_T) return launch_kind<R, M, KIND_ROWS_T>(ft, a, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename R, int M>
+static hipError_t correct_m(int kind, const PassArgs &a, int grid, hipStream_t st) {
+    if (kind == KIND_ROWS) {
+        hipLaunchKernelGGL((correct_kernel<R, M, KIND_ROWS>), dim3(grid), dim3(kCorrThreads), 0, st, a);
+        return hipGetLastError();
+    }
+    if constexpr (M >= 64) {
+        if (kind == KIND_COLS) {
+            hipLaunchKernelGGL((correct_kernel<R, M, KIND_COLS>), dim3(grid), dim3(kCorrThreads), 0, st, a);
+            return hipGetLastError();
+        }
+        if (kind == KIND_ROWS_T) {
+            hipLaunchKernelGGL((correct_kernel<R, M, KIND_ROWS_T>), dim3(grid), dim3(kCorrThreads), 0, st, a);
+            return hipGetLastError();
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename R, typename F>
+static hipError_t by_m(int M, F &&f) {
+    switch (M) {
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        case 16: return f(std::integral_constant<int, 16>{});
+        case 32: return f(std::integral_constant<int, 32>{});
+        case 64: return f(std::integral_constant<int, 64>{});
+        case 128: return f(std::integral_constant<int, 128>{});
+        case 256: return f(std::integral_constant<int, 256>{});
+        case 512: return f(std::integral_constant<int, 512>{});
+        case 1024: return f(std::integral_constant<int, 1024>{});
+        case 2048: return f(std::integral_constant<int, 2048>{});
+        case 4096: return f(std::integral_constant<int, 4096>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pass(int fp64, int M, int kind, int ft, const PassArgs &a, int grid, hipStream_t st) {
+    if (fp64)
+        return by_m<double>(M, [&](auto m) { return launch_m<double, decltype(m)::value>(kind, ft, a, grid, st); });
+    return by_m<float>(M, [&](auto m) { return launch_m<float, decltype(m)::value>(kind, ft, a, grid, st); });
+}
+
+hipError_t launch_correct(int fp64, int M, int kind, const PassArgs &a, int grid, hipStream_t st) {
+    if (fp64) return by_m<double>(M, [&](auto m) { return correct_m<double, decltype(m)::value>(kind, a, grid, st); });
+    return by_m<float>(M, [&](auto m) { return correct_m<float, decltype(m)::value>(kind, a, grid, st); });
+}
+
+hipError_t launch_reset(DevReport *rep, hipStream_t st) {
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, st, rep);
+    return hipGetLastError();
+}
+
+}  // namespace tfft

@@ -1,0 +1,557 @@
+// Host side of the fault-tolerant batched FFT: plans, tables, the C ABI.
+//
+// Every twiddle and checksum vector is generated here in binary64 from exact
+// integer angle arguments and rounded once to the element type
+// (TurboFFT Section IV-A.3 keeps twiddles in global memory because computing
+// them in the kernel costs time; here they are tables for both precisions).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/tfft.h"
+#include "tfft_internal.h"
+
+using namespace tfft;
+using cd = std::complex<double>;
+
+namespace {
+
+// exp(-2 pi i t / n) for integers t, n.  The argument is split into a
+// quadrant q and a remainder r (4 t = q n + r, 0 <= r < n, exact integer
+// arithmetic) so libm only sees angles in [0, pi/4]; the quadrant is applied
+// as an exact multiplication by (-i)^q.
+cd unit_root(int64_t t, int64_t n) {
+    t %= n;
+    if (t < 0) t += n;
+    const __int128 four_t = (__int128)4 * t;
+    const int q = (int)(four_t / n);
+    const int64_t r = (int64_t)(four_t - (__int128)q * n);  // angle within quadrant = (pi/2) r / n
+    double c, s;
+    if (2 * r <= n) {
+        const double ang = (M_PI / 2.0) * ((double)r / (double)n);
+        c = std::cos(ang);
+        s = std::sin(ang);
+    } else {
+        const double ang = (M_PI / 2.0) * ((double)(n - r) / (double)n);
+        c = std::sin(ang);
+        s = std::cos(ang);
+    }
+    if (r == 0) {
+        c = 1.0;
+        s = 0.0;
+    }
+    // exp(-i (q pi/2 + phi)) = (-i)^q (c - i s)
+    cd w(c, -s);
+    switch (q & 3) {
+        case 1: w = cd(w.imag(), -w.real()); break;    // * (-i)
+        case 2: w = cd(-w.real(), -w.imag()); break;   // * (-1)
+        case 3: w = cd(-w.imag(), w.real()); break;    // * (+i)
+        default: break;
+    }
+    return w;
+}
+
+struct PassPlan {
+    int M = 0, kind = 0, E = 0, C = 0, G = 0, rb = 1, stages = 0;
+    int64_t n_strips = 1, n_groups = 0;
+    int grid = 0;
+    void *d_stw = nullptr;       // element-type stage twiddles
+    double *d_stw64 = nullptr;   // fp64 stage twiddles
+    double *d_cfwd = nullptr;    // checksum vector, forward
+    double *d_cinv = nullptr;    // checksum vector, inverse (scaled for the last pass)
+    double *d_cinv_unscaled = nullptr;
+    int32_t *d_fault_head = nullptr;
+    DevFault *d_faults = nullptr;
+    double tau_coef = 0.0;
+};
+
+}  // namespace
+
+struct tfft_plan_s {
+    int device = 0;
+    int64_t n = 0, batch = 0;
+    int dtype = 0;
+    uint32_t flags = 0;
+    double kappa = 16.0;
+    int passes = 0;
+    int n1 = 0, n2 = 0;
+    PassPlan pass[2];
+    double *d_itw_lo = nullptr, *d_itw_hi = nullptr;
+    int itw_bits = 0;
+    void *d_work = nullptr;
+    size_t work_bytes = 0;
+    DevReport *d_rep = nullptr;
+    DevRecord *d_recs = nullptr;
+    int64_t rec_cap = 0;
+    hipStream_t last_stream = nullptr;
+    int executed = 0;
+    int last_mode = 0;
+    int64_t nfaults = 0;
+};
+
+namespace {
+
+int ilog2_64(int64_t x) {
+    int k = 0;
+    while ((int64_t(1) << k) < x) ++k;
+    return k;
+}
+
+template <typename T>
+int upload(T **dst, const std::vector<T> &v) {
+    if (hipMalloc((void **)dst, sizeof(T) * std::max<size_t>(1, v.size())) != hipSuccess) {
+        *dst = nullptr;
+        return TFFT_E_NOMEM;
+    }
+    if (!v.empty() && hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return TFFT_E_HIP;
+    return TFFT_OK;
+}
+
+int default_group(int M) {
+    if (M >= 4096) return 16;
+    if (M >= 2048) return 32;
+    return 64;
+}
+
+// c_n = s sum_k w_3^k w_M^{+-k n}.  Each term is w_{3M}^{k q} with
+// q = (M +- 3n) mod 3M, so the sum is geometric: (1 - w_3^M) / (1 - w_{3M}^q).
+// Writing w_{3M}^q = v^2 with v = w_{6M}^q, 1 - v^2 = v (conj(v) - v) =
+// -2i Im(v) v, which has no cancellation; v comes from the exactly reduced
+// root, so each entry is within a few ulp.
+std::vector<double> checksum_vec(int M, bool inverse, double scale) {
+    std::vector<double> out(2 * (size_t)M);
+    const cd num = 1.0 - unit_root(M % 3, 3);
+    const int64_t M3 = 3 * (int64_t)M;
+    for (int n = 0; n < M; ++n) {
+        int64_t q = ((int64_t)M + (inverse ? -3 : 3) * (int64_t)n) % M3;
+        if (q < 0) q += M3;
+        const cd v = unit_root(q, 2 * M3);
+        const cd c = scale * num * std::conj(v) * cd(0.0, 1.0 / (2.0 * v.imag()));
+        out[2 * n] = c.real();
+        out[2 * n + 1] = c.imag();
+    }
+    return out;
+}
+
+int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser) {
+    PassPlan &P = p->pass[idx];
+    const int fp64 = p->dtype == TFFT_C128;
+    P.M = M;
+    P.kind = kind;
+    P.E = cfg_E(fp64, M);
+    P.C = cfg_C(fp64, M, kind);
+    P.stages = n_stages(M, P.E);
+    const int G0 = Guser > 0 ? Guser : (kind == KIND_ROWS ? default_group(M) : 16);
+    if (kind == KIND_ROWS) {
+        if (G0 % P.C != 0) return TFFT_E_UNSUPPORTED;
+        P.G = G0;
+        P.rb = 1;
+        P.n_strips = 1;
+        P.n_groups = (p->batch + P.G - 1) / P.G;
+    } else {
+        const int64_t n_sub = kind == KIND_COLS ? p->n2 : p->n1;
+        P.rb = (int)std::max<int64_t>(1, std::min<int64_t>(std::max(1, G0 / P.C), p->batch));
+        P.G = P.C * P.rb;
+        P.n_strips = n_sub / P.C;
+        P.n_groups = P.n_strips * ((p->batch + P.rb - 1) / P.rb);
+    }
+    int64_t grid = std::min<int64_t>(P.n_groups, 2048);
+    if (grid >= 8) grid = (grid + 7) / 8 * 8;
+    P.grid = (int)std::max<int64_t>(1, grid);
+    const double u = fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+    P.tau_coef = p->kappa * u * std::sqrt(std::max(1.0, (double)ilog2_64(M))) * std::sqrt((double)M);
+
+    // stage twiddles w_M^t, t < M
+    std::vector<double> w64(2 * (size_t)M);
+    for (int t = 0; t < M; ++t) {
+        const cd w = unit_root(t, M);
+        w64[2 * t] = w.real();
+        w64[2 * t + 1] = w.imag();
+    }
+    int rc;
+    if (fp64) {
+        if ((rc = upload((double **)&P.d_stw, w64)) != TFFT_OK) return rc;
+    } else {
+        std::vector<float> w32(w64.begin(), w64.end());
+        if ((rc = upload((float **)&P.d_stw, w32)) != TFFT_OK) return rc;
+    }
+    if ((rc = upload(&P.d_stw64, w64)) != TFFT_OK) return rc;
+    const bool last = idx == p->passes - 1;
+    if ((rc = upload(&P.d_cfwd, checksum_vec(M, false, 1.0))) != TFFT_OK) return rc;
+    if ((rc = upload(&P.d_cinv_unscaled, checksum_vec(M, true, 1.0))) != TFFT_OK) return rc;
+    if ((rc = upload(&P.d_cinv, checksum_vec(M, true, last ? 1.0 / (double)p->n : 1.0))) != TFFT_OK) return rc;
+    return TFFT_OK;
+}
+
+void free_plan(tfft_plan_s *p) {
+    if (!p) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(p->device);
+    for (auto &P : p->pass) {
+        (void)hipFree(P.d_stw);
+        (void)hipFree(P.d_stw64);
+        (void)hipFree(P.d_cfwd);
+        (void)hipFree(P.d_cinv);
+        (void)hipFree(P.d_cinv_unscaled);
+        (void)hipFree(P.d_fault_head);
+        (void)hipFree(P.d_faults);
+    }
+    (void)hipFree(p->d_itw_lo);
+    (void)hipFree(p->d_itw_hi);
+    (void)hipFree(p->d_work);
+    (void)hipFree(p->d_rep);
+    (void)hipFree(p->d_recs);
+    (void)hipSetDevice(cur);
+    delete p;
+}
+
+int clear_faults(tfft_plan_s *p) {
+    for (auto &P : p->pass) {
+        (void)hipFree(P.d_fault_head);
+        (void)hipFree(P.d_faults);
+        P.d_fault_head = nullptr;
+        P.d_faults = nullptr;
+    }
+    p->nfaults = 0;
+    return TFFT_OK;
+}
+
+struct Guard {
+    int prev = 0;
+    explicit Guard(int dev) {
+        (void)hipGetDevice(&prev);
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~Guard() {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        if (cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, bool inverse) {
+    if (!p || !d_in || !d_out) return TFFT_E_INVALID;
+    if (mode < TFFT_FT_OFF || mode > TFFT_FT_CORRECT) return TFFT_E_INVALID;
+    if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 15)) return TFFT_E_INVALID;
+    const size_t esz = p->dtype == TFFT_C128 ? 16 : 8;
+    const size_t bytes = (size_t)p->n * (size_t)p->batch * esz;
+    const uintptr_t a = (uintptr_t)d_in, b = (uintptr_t)d_out;
+    if ((a < b ? b - a : a - b) < bytes) return TFFT_E_INVALID;
+    Guard guard(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int fp64 = p->dtype == TFFT_C128;
+    const int ft = mode != TFFT_FT_OFF;
+    if (launch_reset(p->d_rep, st) != hipSuccess) return TFFT_E_HIP;
+    for (int i = 0; i < p->passes; ++i) {
+        const PassPlan &P = p->pass[i];
+        const bool last = i == p->passes - 1;
+        PassArgs A;
+        std::memset(&A, 0, sizeof(A));
+        A.in = i == 0 ? d_in : p->d_work;
+        A.out = last ? d_out : p->d_work;
+        A.batch = p->batch;
+        A.n = p->n;
+        A.n1 = p->passes == 1 ? (int32_t)p->n : p->n1;
+        A.n2 = p->passes == 1 ? 1 : p->n2;
+        A.G = P.G;
+        A.rb = P.rb;
+        A.n_strips = P.n_strips;
+        A.n_groups = P.n_groups;
+        A.conj_in = inverse ? 1 : 0;
+        A.conj_out = inverse ? 1 : 0;
+        A.out_scale = (inverse && last && !(p->flags & TFFT_INVERSE_UNSCALED)) ? 1.0 / (double)p->n : 1.0;
+        A.cvec = !inverse ? P.d_cfwd : ((p->flags & TFFT_INVERSE_UNSCALED) ? P.d_cinv_unscaled : P.d_cinv);
+        A.stw = P.d_stw;
+        A.stw64 = P.d_stw64;
+        A.itw_lo = p->d_itw_lo;
+        A.itw_hi = p->d_itw_hi;
+        A.itw_bits = p->itw_bits;
+        A.pass = i;
+        A.tau_coef = P.tau_coef * A.out_scale;  // the outputs' rounding noise scales with them
+        A.rep = p->d_rep;
+        A.recs = p->d_recs;
+        A.rec_cap = p->rec_cap;
+        A.fault_head = P.d_fault_head;
+        A.faults = P.d_faults;
+        if (launch_pass(fp64, P.M, P.kind, ft, A, P.grid, st) != hipSuccess) return TFFT_E_HIP;
+        if (mode == TFFT_FT_CORRECT) {
+            if (launch_correct(fp64, P.M, P.kind, A, 64, st) != hipSuccess) return TFFT_E_HIP;
+        }
+    }
+    p->last_stream = st;
+    p->executed = 1;
+    p->last_mode = mode;
+    return TFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tfft_version(void) { return TFFT_VERSION; }
+
+const char *tfft_status_string(int s) {
+    switch (s) {
+        case TFFT_OK: return "ok";
+        case TFFT_UNCORRECTABLE: return "completed; a flagged group could not be corrected";
+        case TFFT_E_INVALID: return "invalid argument";
+        case TFFT_E_UNSUPPORTED: return "unsupported configuration";
+        case TFFT_E_NOMEM: return "out of memory";
+        case TFFT_E_HIP: return "HIP runtime error";
+        case TFFT_E_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+int tfft_plan_create_with(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_options *opt) {
+    if (!out) return TFFT_E_INVALID;
+    *out = nullptr;
+    if (n < 2 || n > (int64_t(1) << 24) || (n & (n - 1)) != 0) return TFFT_E_INVALID;
+    if (batch < 1 || dtype < TFFT_C64 || dtype > TFFT_C128) return TFFT_E_INVALID;
+    const size_t esz = dtype == TFFT_C128 ? 16 : 8;
+    if ((uint64_t)batch > (UINT64_MAX / 4) / ((uint64_t)n * esz)) return TFFT_E_INVALID;
+    const uint32_t flags = opt ? opt->flags : 0;
+    const int Guser = opt ? opt->group : 0;
+    if (Guser < 0 || Guser > 64 || (Guser & (Guser - 1)) != 0) return TFFT_E_INVALID;
+    if (opt && (opt->kappa < 0 || !std::isfinite(opt->kappa))) return TFFT_E_INVALID;
+    if (flags & ~(uint32_t)TFFT_INVERSE_UNSCALED) return TFFT_E_INVALID;
+
+    tfft_plan_s *p = new (std::nothrow) tfft_plan_s();
+    if (!p) return TFFT_E_NOMEM;
+    (void)hipGetDevice(&p->device);
+    p->n = n;
+    p->batch = batch;
+    p->dtype = dtype;
+    p->flags = flags;
+    p->kappa = (opt && opt->kappa > 0) ? opt->kappa : 16.0;
+    const int k = ilog2_64(n);
+    int rc = TFFT_OK;
+    if (n <= 4096) {
+        p->passes = 1;
+        p->n1 = (int)n;
+        p->n2 = 1;
+        rc = build_pass(p, 0, (int)n, KIND_ROWS, Guser);
+    } else {
+        p->passes = 2;
+        const int k1 = k / 2, k2 = k - k1;
+        p->n1 = 1 << k1;
+        p->n2 = 1 << k2;
+        rc = build_pass(p, 0, p->n1, KIND_COLS, Guser);
+        if (rc == TFFT_OK) rc = build_pass(p, 1, p->n2, KIND_ROWS_T, Guser);
+        if (rc == TFFT_OK) {
+            // w_N^t = lo[t mod 2^b] * hi[t >> b]
+            p->itw_bits = (k + 1) / 2;
+            const int64_t nlo = int64_t(1) << p->itw_bits, nhi = n >> p->itw_bits;
+            std::vector<double> lo(2 * (size_t)nlo), hi(2 * (size_t)nhi);
+            for (int64_t t = 0; t < nlo; ++t) {
+                const cd w = unit_root(t, n);
+                lo[2 * t] = w.real();
+                lo[2 * t + 1] = w.imag();
+            }
+            for (int64_t t = 0; t < nhi; ++t) {
+                const cd w = unit_root(t << p->itw_bits, n);
+                hi[2 * t] = w.real();
+                hi[2 * t + 1] = w.imag();
+            }
+            rc = upload(&p->d_itw_lo, lo);
+            if (rc == TFFT_OK) rc = upload(&p->d_itw_hi, hi);
+            if (rc == TFFT_OK) {
+                p->work_bytes = (size_t)n * (size_t)batch * esz;
+                if (hipMalloc(&p->d_work, p->work_bytes) != hipSuccess) {
+                    p->d_work = nullptr;
+                    rc = TFFT_E_NOMEM;
+                }
+            }
+        }
+    }
+    if (rc == TFFT_OK) {
+        int64_t cap = 0;
+        for (int i = 0; i < p->passes; ++i) cap += p->pass[i].n_groups;
+        p->rec_cap = std::max<int64_t>(1, cap);
+        if (hipMalloc((void **)&p->d_rep, sizeof(DevReport)) != hipSuccess ||
+            hipMalloc((void **)&p->d_recs, sizeof(DevRecord) * (size_t)p->rec_cap) != hipSuccess)
+            rc = TFFT_E_NOMEM;
+        else if (hipMemset(p->d_rep, 0, sizeof(DevReport)) != hipSuccess)
+            rc = TFFT_E_HIP;
+    }
+    if (rc != TFFT_OK) {
+        free_plan(p);
+        return rc;
+    }
+    *out = p;
+    return TFFT_OK;
+}
+
+int tfft_plan_create(tfft_plan *out, int64_t n, int64_t batch, int dtype, uint32_t flags) {
+    tfft_options o;
+    std::memset(&o, 0, sizeof(o));
+    o.flags = flags;
+    return tfft_plan_create_with(out, n, batch, dtype, &o);
+}
+
+int tfft_plan_destroy(tfft_plan p) {
+    free_plan(p);
+    return TFFT_OK;
+}
+
+int tfft_exec_forward(tfft_plan p, const void *d_in, void *d_out, int ft_mode, void *hip_stream) {
+    return exec(p, d_in, d_out, ft_mode, hip_stream, false);
+}
+
+int tfft_exec_inverse(tfft_plan p, const void *d_in, void *d_out, int ft_mode, void *hip_stream) {
+    return exec(p, d_in, d_out, ft_mode, hip_stream, true);
+}
+
+int tfft_get_report(tfft_plan p, tfft_counts *counts, tfft_record *recs, int64_t cap) {
+    if (!p || cap < 0 || (cap > 0 && !recs)) return TFFT_E_INVALID;
+    if (!p->executed) return TFFT_E_STATE;
+    Guard guard(p->device);
+    if (hipStreamSynchronize(p->last_stream) != hipSuccess) return TFFT_E_HIP;
+    DevReport h;
+    if (hipMemcpy(&h, p->d_rep, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return TFFT_E_HIP;
+    const int64_t nrec = std::min<int64_t>((int64_t)h.n_flag, p->rec_cap);
+    std::vector<DevRecord> dr((size_t)nrec);
+    if (nrec > 0 &&
+        hipMemcpy(dr.data(), p->d_recs, sizeof(DevRecord) * (size_t)nrec, hipMemcpyDeviceToHost) != hipSuccess)
+        return TFFT_E_HIP;
+    std::sort(dr.begin(), dr.end(), [](const DevRecord &x, const DevRecord &y) {
+        return x.pass != y.pass ? x.pass < y.pass : x.group < y.group;
+    });
+    int64_t groups = 0;
+    if (p->last_mode != TFFT_FT_OFF)
+        for (int i = 0; i < p->passes; ++i) groups += p->pass[i].n_groups;
+    if (counts) {
+        counts->groups_checked = groups;
+        counts->detected = (int64_t)h.n_flag;
+        counts->corrected = (int64_t)h.corrected;
+        counts->uncorrectable = (int64_t)h.uncorrectable;
+        counts->benign = (int64_t)h.benign;
+        counts->n_records = nrec;
+        counts->dropped = (int64_t)h.n_flag - nrec;
+    }
+    for (int64_t i = 0; i < std::min(cap, nrec); ++i) {
+        const DevRecord &d = dr[(size_t)i];
+        const PassPlan &P = p->pass[d.pass];
+        tfft_record &r = recs[i];
+        const int mem = d.member >= 0 ? d.member : 0;
+        if (P.kind == KIND_ROWS) {
+            r.signal = d.group * P.G + mem;
+            r.sub = 0;
+        } else {
+            const int64_t strip = d.group % P.n_strips, bblock = d.group / P.n_strips;
+            r.signal = bblock * P.rb + mem / P.C;
+            r.sub = strip * P.C + mem % P.C;
+        }
+        r.group = d.group;
+        r.pass = d.pass;
+        r.member = d.member;
+        r.action = d.action;
+        r.method = d.method;
+        r.residual = std::sqrt(d.d1r * d.d1r + d.d1i * d.d1i);
+        r.threshold = d.tau;
+        const double den = d.d1r * d.d1r + d.d1i * d.d1i;
+        r.ratio_re = (d.d2r * d.d1r + d.d2i * d.d1i) / den;
+        r.ratio_im = (d.d2i * d.d1r - d.d2r * d.d1i) / den;
+    }
+    const bool bad = h.uncorrectable > 0 || (p->last_mode == TFFT_FT_CORRECT && (int64_t)h.n_flag > nrec);
+    return bad ? TFFT_UNCORRECTABLE : TFFT_OK;
+}
+
+int tfft_set_faults(tfft_plan p, const tfft_fault *specs, int64_t n) {
+    if (!p || n < 0 || (n > 0 && !specs)) return TFFT_E_INVALID;
+    Guard guard(p->device);
+    if (hipDeviceSynchronize() != hipSuccess) return TFFT_E_HIP;
+    clear_faults(p);
+    if (n == 0) return TFFT_OK;
+    std::vector<std::vector<DevFault>> per(p->passes);
+    for (int64_t f = 0; f < n; ++f) {
+        const tfft_fault &s = specs[f];
+        if (s.signal < 0 || s.signal >= p->batch || s.pass < 0 || s.pass >= p->passes) return TFFT_E_INVALID;
+        if (s.index < 0 || s.index >= p->n) return TFFT_E_INVALID;
+        const PassPlan &P = p->pass[s.pass];
+        if (s.stage < -1 || s.stage >= P.stages) return TFFT_E_INVALID;
+        const int M = P.M, E = P.E, T = M / E;
+        int64_t g, pos;
+        int b;
+        if (P.kind == KIND_ROWS) {
+            g = s.signal / P.G;
+            b = (int)(s.signal % P.G);
+            pos = s.index;
+        } else {
+            const int64_t sub = s.index / M;
+            pos = s.index % M;
+            const int64_t strip = sub / P.C, bblock = s.signal / P.rb;
+            g = bblock * P.n_strips + strip;
+            b = (int)((s.signal % P.rb) * P.C + sub % P.C);
+        }
+        DevFault d;
+        std::memset(&d, 0, sizeof(d));
+        d.group = g;
+        d.member = b;
+        d.stage = s.stage;
+        d.dre = s.dre;
+        d.dim = s.dim;
+        if (s.stage < 0) {
+            d.j = (int)(pos % T);
+            d.m = (int)(pos / T);
+        } else {
+            const int RAD = stage_radix(M, E, s.stage), NS = stage_ns(M, E, s.stage), NB = E / RAD;
+            const int64_t q = (pos / NS) % RAD;
+            const int64_t i = (pos / ((int64_t)NS * RAD)) * NS + pos % NS;
+            d.j = (int)(i % T);
+            d.m = (int)(i / T + q * NB);
+        }
+        per[s.pass].push_back(d);
+    }
+    for (int i = 0; i < p->passes; ++i) {
+        auto &v = per[i];
+        if (v.empty()) continue;
+        PassPlan &P = p->pass[i];
+        std::stable_sort(v.begin(), v.end(), [](const DevFault &x, const DevFault &y) { return x.group < y.group; });
+        std::vector<int32_t> head((size_t)P.n_groups, -1);
+        for (size_t k = 0; k < v.size(); ++k) {
+            v[k].next = (k + 1 < v.size() && v[k + 1].group == v[k].group) ? (int32_t)(k + 1) : -1;
+            if (k == 0 || v[k - 1].group != v[k].group) head[(size_t)v[k].group] = (int32_t)k;
+        }
+        int rc = upload(&P.d_fault_head, head);
+        if (rc == TFFT_OK) rc = upload(&P.d_faults, v);
+        if (rc != TFFT_OK) {
+            clear_faults(p);
+            return rc;
+        }
+    }
+    p->nfaults = n;
+    return TFFT_OK;
+}
+
+int tfft_plan_info(tfft_plan p, tfft_plan_desc *info) {
+    if (!p || !info) return TFFT_E_INVALID;
+    std::memset(info, 0, sizeof(*info));
+    info->n = p->n;
+    info->batch = p->batch;
+    info->dtype = p->dtype;
+    info->passes = p->passes;
+    for (int i = 0; i < p->passes; ++i) {
+        const PassPlan &P = p->pass[i];
+        info->pass_len[i] = P.M;
+        info->group[i] = P.G;
+        info->elems_per_thread[i] = P.E;
+        info->tile_signals[i] = P.C;
+        info->stages[i] = P.stages;
+        for (int s = 0; s < P.stages && s < 8; ++s) info->radices[i][s] = stage_radix(P.M, P.E, s);
+        info->groups[i] = P.n_groups;
+    }
+    info->workspace_bytes = p->work_bytes;
+    info->kappa = p->kappa;
+    return TFFT_OK;
+}
+
+}  // extern "C"

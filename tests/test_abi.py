@@ -1,0 +1,82 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/tfft.h; argument validation that needs no device work (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tfft.h")
+
+
+@pytest.fixture(scope="module")
+def tf():
+    lib = os.path.join(ROOT, "paper_2405_02520_amd", "libtfft.so")
+    if not os.path.exists(lib):
+        import runpy
+        runpy.run_path(os.path.join(ROOT, "paper_2405_02520_amd", "build.py"), run_name="__main__")
+    import paper_2405_02520_amd
+
+    return paper_2405_02520_amd
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tfft_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["tfft_plan_create", "tfft_plan_create_with", "tfft_plan_destroy", "tfft_exec_forward",
+              "tfft_exec_inverse", "tfft_get_report", "tfft_set_faults", "tfft_plan_info",
+              "tfft_status_string", "tfft_version"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(tf):
+    lib = ctypes.CDLL(tf.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(tf.EXPORTED) == set(declared_functions())
+
+
+def test_version_and_status_strings(tf):
+    assert tf.tfft_version() == 1
+    assert tf.tfft_status_string(tf.OK) == b"ok"
+    assert b"invalid" in tf.tfft_status_string(tf.E_INVALID)
+    assert tf.tfft_status_string(12345) == b"unknown status"
+
+
+@pytest.mark.parametrize("n,batch,dtype", [(0, 1, 0), (3, 1, 0), (12, 4, 0), (1 << 25, 1, 0), (1024, 0, 0),
+                                           (1024, -5, 0), (1024, 1, 2), (1024, 1, -1)])
+def test_plan_create_rejects_bad_arguments(tf, n, batch, dtype):
+    h = ctypes.c_void_p(1234)
+    st = tf.tfft_plan_create(ctypes.byref(h), n, batch, dtype, 0)
+    assert st == tf.E_INVALID
+    assert not h.value
+
+
+def test_plan_create_rejects_bad_options(tf):
+    h = ctypes.c_void_p()
+    for group, kappa, flags in [(3, 0.0, 0), (128, 0.0, 0), (-1, 0.0, 0), (0, -1.0, 0), (0, float("nan"), 0),
+                                (0, 0.0, 1 << 7)]:
+        opt = tf.tfft_options(flags=flags, group=group, kappa=kappa)
+        assert tf.tfft_plan_create_with(ctypes.byref(h), 1024, 4, 0, ctypes.byref(opt)) == tf.E_INVALID
+    assert tf.tfft_plan_create(None, 1024, 4, 0, 0) == tf.E_INVALID
+
+
+def test_null_plan_is_rejected(tf):
+    assert tf.tfft_plan_destroy(None) == tf.OK
+    assert tf.tfft_exec_forward(None, 16, 16, 0, None) == tf.E_INVALID
+    assert tf.tfft_exec_inverse(None, 16, 16, 0, None) == tf.E_INVALID
+    assert tf.tfft_get_report(None, None, None, 0) == tf.E_INVALID
+    assert tf.tfft_set_faults(None, None, 0) == tf.E_INVALID
+    assert tf.tfft_plan_info(None, None) == tf.E_INVALID
+
+
+def test_record_layouts_match_header(tf):
+    assert ctypes.sizeof(tf.tfft_record) == 8 * 3 + 4 * 4 + 8 * 4
+    assert ctypes.sizeof(tf.tfft_fault) == 8 + 4 + 4 + 8 + 16
+    assert ctypes.sizeof(tf.tfft_counts) == 7 * 8

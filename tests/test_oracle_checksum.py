@@ -41,10 +41,33 @@ def gauss_int(seed, *shape, lo=-5, hi=6):
 def test_checksum_vector_closed_form(m, inverse):
     s = 1.0 / m if inverse else 1.0
     c = oracle.checksum_vector(m, inverse, s)
-    d = oracle.checksum_vector_direct(m, inverse, s)
-    assert np.max(np.abs(c - d)) <= 1e-13 * m * s * m
+    d = oracle.checksum_vector_direct(m, inverse, s, exact_sum=True)
+    # each binary64 term of the direct sum is off by about an ulp, so the two
+    # agree to a random walk of m such errors
+    assert np.max(np.abs(c - d)) <= 32 * np.finfo(float).eps * math.sqrt(m) * s
     assert abs(np.linalg.norm(c) - m * s) <= 1e-12 * m * s
     assert np.min(np.abs(c)) > 0.8 * s   # never zero: every single fault is seen
+
+
+@pytest.mark.parametrize("m", [8, 64, 256])
+@pytest.mark.parametrize("inverse", [False, True])
+def test_checksum_vector_vs_high_precision_direct_sum(m, inverse):
+    """Every entry, small or large, within a few ulp of the defining sum
+    sum_k w_3^k w_m^{+-kn} evaluated term by term in 40-digit arithmetic."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    c = oracle.checksum_vector(m, inverse)
+    w3 = mpmath.exp(-2j * mpmath.pi / 3)
+    sgn = 1 if inverse else -1
+    worst = 0.0
+    for n in range(m):
+        z = w3 * mpmath.exp(sgn * 2j * mpmath.pi * n / m)
+        acc, zk = mpmath.mpc(0), mpmath.mpc(1)
+        for _ in range(m):
+            acc += zk
+            zk *= z
+        worst = max(worst, float(abs(mpmath.mpc(c[n]) - acc) / abs(acc)))
+    assert worst <= 4 * np.finfo(float).eps
 
 
 def test_encoding_vector_is_w3_powers():
