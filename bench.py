@@ -1,0 +1,278 @@
+"""Benchmark of the fault-tolerant batched C2C FFT on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtypes c64,c128] [--kmin 8] [--kmax 24]
+                    [--no-cpu-baseline] [--no-extras]
+
+Workload (the throughput sweep): forward C2C transforms of length N = 2^k for
+k = 8..24 with N * batch = 2^28 elements in complex64 and 2^27 in complex128
+(2 GiB in + 2 GiB out each), inputs i.i.d. U[-1, 1) drawn once per precision
+and viewed as [batch][N]; fault tolerance CORRECT (two-sided checksum, no
+faults injected).  One step = one forward transform of every (precision, k)
+of the sweep with inputs resident in HBM.
+
+Printed: one JSON line with the metric (nominal GFLOP/s = sum of 5 N log2 N
+batch over the step / step time), the roofline of the dominant kernel from
+HIP events on the execution stream, and the oracle's CPU throughput on a
+bounded sample.  The per-size breakdown, checksum overhead (FT CORRECT vs OFF,
+same kernels) and the cost of running with one injected fault per 256 signals
+are in the same line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+METRIC = "GFLOP/s & HBM GB/s, batched C2C FFT with checksum; FT overhead % vs no-FT"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dtypes", default="c64,c128")
+    ap.add_argument("--kmin", type=int, default=8)
+    ap.add_argument("--kmax", type=int, default=24)
+    ap.add_argument("--log2-elems", type=int, default=28, help="log2 of N*batch for complex64 (complex128: one less)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FT off / faulty overhead runs")
+    ap.add_argument("--extra-reps", type=int, default=5)
+    return ap.parse_args()
+
+
+def cpu_baseline(sizes):
+    """The FP64 oracle (C radix-2, OpenMP over signals) on a bounded sample of
+    the same sweep: 2^22 elements of each size (one signal when N > 2^22)."""
+    import numpy as np
+
+    import oracle
+    import tfft_inputs as inputs
+
+    threads = oracle.max_threads()
+    flops = 0.0
+    t_total = 0.0
+    nsig_total = 0
+    for (dt, k) in sizes:
+        n = 1 << k
+        b = max(1, (1 << 22) // n)
+        x = inputs.uniform(inputs.sweep_seed(k, dt == "c128"), b, n, np.complex128)
+        t0 = time.perf_counter()
+        oracle.fft(x)
+        t_total += time.perf_counter() - t0
+        flops += 5.0 * n * k * b
+        nsig_total += b
+    return {"value": flops / t_total / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 recursive radix-2 oracle, {len(sizes)} sizes of the sweep, 2^22 elements per size "
+                      f"(one signal for N > 2^22; OpenMP over signals), {nsig_total} signals, {t_total:.1f} s",
+            "seconds": t_total}
+
+
+def pmc_traffic(kernel_key):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    src = os.path.join(ROOT, "paper_2405_02520_amd", "csrc", "tfft_kernels.hip")
+    try:
+        d = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if d.get("kernel_source_sha256") != sha:
+            return None
+        return d["entries"].get(kernel_key)
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; a batched FFT shards on the batch axis with no "
+              "exchange (see DESIGN.md).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2405_02520_amd as tf
+    import tfft_inputs as inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    dtypes = [d for d in args.dtypes.split(",") if d]
+    ks = list(range(args.kmin, args.kmax + 1))
+    sizes = [(dt, k) for dt in dtypes for k in ks]
+    esz = {"c64": 8, "c128": 16}
+    log2e = {"c64": args.log2_elems, "c128": args.log2_elems - 1}
+    tdt = {"c64": torch.complex64, "c128": torch.complex128}
+
+    # inputs: one draw per precision, resident in HBM
+    xin = {}
+    for dt in dtypes:
+        e = 1 << log2e[dt]
+        x = inputs.uniform(inputs.sweep_seed(0, dt == "c128"), 1, e, np.complex64 if dt == "c64" else np.complex128)
+        xin[dt] = torch.from_numpy(x.reshape(-1)).to(dev)
+        del x
+    out_bytes = max(esz[dt] << log2e[dt] for dt in dtypes)
+    ybuf = torch.empty(out_bytes, dtype=torch.uint8, device=dev)
+
+    plans, xs, ys = {}, {}, {}
+    for dt, k in sizes:
+        n = 1 << k
+        b = (1 << log2e[dt]) // n
+        p = tf.Plan(n, b, dt)
+        p.set_timing(True)
+        plans[(dt, k)] = p
+        xs[(dt, k)] = xin[dt].view(b, n)
+        ys[(dt, k)] = ybuf[: n * b * esz[dt]].view(tdt[dt]).view(b, n)
+
+    def step():
+        for key in sizes:
+            plans[key].forward(xs[key], out=ys[key], ft_mode="correct", stream=stream)
+
+    # warm-up; the first warm-up step also checks Parseval on every size
+    sanity = {}
+    for w in range(max(1, args.warmup)):
+        for key in sizes:
+            plans[key].forward(xs[key], out=ys[key], ft_mode="correct", stream=stream)
+            if w == 0:
+                dt, k = key
+                x, y = xs[key], ys[key]
+                ex = torch.sum(x.real.double() ** 2 + x.imag.double() ** 2) * (1 << k)
+                ey = torch.sum(y.real.double() ** 2 + y.imag.double() ** 2)
+                sanity[f"{dt}_k{k}"] = abs(float(ey / ex) - 1.0)
+                c, _ = plans[key].report()
+                if c["detected"]:
+                    raise SystemExit(f"clean run flagged {c['detected']} groups at {key}")
+    torch.cuda.synchronize()
+    worst_parseval = max(sanity.values())
+    if worst_parseval > 1e-4:
+        raise SystemExit(f"Parseval check failed: {sanity}")
+
+    # timed region: exactly K steps
+    kern = {key: [] for key in sizes}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        for key in sizes:
+            pm, cm = plans[key].timings()
+            kern[key].append((pm, cm))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    flops_step = sum(5.0 * (1 << k) * k * ((1 << log2e[dt]) >> k) for dt, k in sizes)
+    value = flops_step / (ms_per_step * 1e-3) / 1e9
+
+    # per-size breakdown and the dominant kernel
+    breakdown = {}
+    dom = None
+    for dt, k in sizes:
+        n = 1 << k
+        b = (1 << log2e[dt]) // n
+        rows = kern[(dt, k)]
+        passes = len(rows[0][0])
+        pass_ms = [sum(r[0][i] for r in rows) / len(rows) for i in range(passes)]
+        corr_ms = [sum(r[1][i] for r in rows) / len(rows) for i in range(passes)]
+        tot = sum(pass_ms) + sum(corr_ms)
+        algo = 2.0 * n * b * esz[dt]
+        breakdown[f"{dt}_k{k}"] = {
+            "ms": round(tot, 4), "pass_ms": [round(v, 4) for v in pass_ms],
+            "correct_ms": [round(v, 4) for v in corr_ms],
+            "gflops": round(5.0 * n * k * b / (tot * 1e-3) / 1e9, 1),
+            "eff_GBps": round(algo / (tot * 1e-3) / 1e9, 1),
+            "pass_GBps": [round(algo / (v * 1e-3) / 1e9, 1) for v in pass_ms],
+        }
+        info = plans[(dt, k)].info()
+        for i, v in enumerate(pass_ms):
+            kind = "rows" if passes == 1 else ("cols" if i == 0 else "rows_t")
+            cand = (v * len(rows), dt, k, i, kind, info["pass_len"][i], algo, v)
+            if dom is None or cand[0] > dom[0]:
+                dom = cand
+    _, ddt, dk, dpass, dkind, dM, dalgo, dms = dom
+    achieved = dalgo / (dms * 1e-3) / 1e9
+    kernel_key = f"pass_kernel<{'float' if ddt == 'c64' else 'double'},{dM},{dkind},FT> {ddt} k={dk} pass={dpass}"
+    tr = pmc_traffic(kernel_key)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
+                "kernel": kernel_key, "algorithmic_bytes_per_launch": int(dalgo), "avg_launch_ms": round(dms, 4)}
+
+    # checksum overhead (same kernels, FT off) and cost of injected faults
+    extras = {}
+    if not args.no_extras:
+        for dt, k in sizes:
+            key = (dt, k)
+            p, x, y = plans[key], xs[key], ys[key]
+            n = 1 << k
+            b = (1 << log2e[dt]) // n
+
+            def timed(mode):
+                ts = []
+                for _ in range(args.extra_reps):
+                    p.forward(x, out=y, ft_mode=mode, stream=stream)
+                    pm, cm = p.timings()
+                    ts.append(sum(pm) + sum(cm))
+                return sorted(ts)[len(ts) // 2]
+
+            t_off = timed("off")
+            t_on = timed("correct")
+            # one fault per aligned block of 256 signals (at least one), on a
+            # final value of a pass, magnitude = RMS of the values there
+            rng = inputs.fault_rng(inputs.sweep_seed(k, dt == "c128"))
+            info = p.info()
+            nf = max(1, b // 256)
+            faults = []
+            for i in range(nf):
+                sig = min(b - 1, i * 256 + int(rng.integers(min(256, b))))
+                ps = int(rng.integers(info["passes"]))
+                plen = info["pass_len"][0] if ps == 0 else n
+                faults.append(dict(signal=sig, pass_=ps, stage=-1, index=int(rng.integers(n)),
+                                   value=math.sqrt(2.0 * plen / 3.0) * complex(0.6, -0.8)))
+            p.set_faults(faults)
+            t_fault = timed("correct")
+            c, recs = p.report()
+            p.set_faults([])
+            extras[f"{dt}_k{k}"] = {
+                "ms_ft_off": round(t_off, 4), "ms_ft_on": round(t_on, 4), "ms_ft_on_faulty": round(t_fault, 4),
+                "ft_overhead_pct": round((t_on / t_off - 1) * 100, 2),
+                "fault_overhead_pct": round((t_fault / t_on - 1) * 100, 2),
+                "faults": nf, "corrected": c["corrected"], "detected": c["detected"],
+            }
+        torch.cuda.synchronize()
+
+    res = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "+".join("f32" if d == "c64" else "f64" for d in dtypes),
+        "data": "synthetic: i.i.d. U[-1,1) complex, seeded",
+        "config": {"workload": f"forward C2C sweep N=2^{args.kmin}..2^{args.kmax}, N*batch=2^{args.log2_elems} "
+                               f"(c64) / 2^{args.log2_elems - 1} (c128), two-sided checksum CORRECT, no faults",
+                   "sizes": len(sizes), "bytes_per_step": int(sum(2 * esz[dt] << log2e[dt] for dt, k in sizes))},
+        "roofline": roofline,
+    }
+    res["effective_GBps"] = round(res["config"]["bytes_per_step"] / (ms_per_step * 1e-3) / 1e9, 1)
+    res["breakdown"] = breakdown
+    if extras:
+        offs = [v["ms_ft_off"] for v in extras.values()]
+        ons = [v["ms_ft_on"] for v in extras.values()]
+        flt = [v["ms_ft_on_faulty"] for v in extras.values()]
+        res["ft_overhead_pct"] = round((sum(ons) / sum(offs) - 1) * 100, 2)
+        res["fault_overhead_pct"] = round((sum(flt) / sum(ons) - 1) * 100, 2)
+        res["extras"] = extras
+    res["parseval_worst_rel"] = worst_parseval
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(sizes)
+    for p in plans.values():
+        p.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

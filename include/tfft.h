@@ -178,6 +178,16 @@ int tfft_set_faults(tfft_plan p, const tfft_fault *specs, int64_t n);
 /* Fill *info with the plan's decomposition and sizes. */
 int tfft_plan_info(tfft_plan p, tfft_plan_desc *info);
 
+/* Measurement instrument.  With timing enabled (enable != 0), every
+ * execution records HIP events on its stream immediately before and after
+ * each kernel launch; tfft_get_timings synchronises that stream and writes
+ * the durations of the last execution in milliseconds: pass_ms[p] for the
+ * transform kernel of pass p and correct_ms[p] for its correction launch
+ * (0 when not launched); each array holds 2 entries, either may be NULL.
+ * E_STATE if timing was off for the last execution. */
+int tfft_set_timing(tfft_plan p, int enable);
+int tfft_get_timings(tfft_plan p, double *pass_ms, double *correct_ms);
+
 /* Static text for a status code. */
 const char *tfft_status_string(int status);
 

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libtfft.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is not built; run `python -m paper_2405_02520_amd.build` (hipcc, gfx950) first")
+        f"{LIB_PATH} is not built; run `python paper_2405_02520_amd/build.py` (hipcc, gfx950) first")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -81,6 +81,8 @@ _sig = {
                         ctypes.c_int),
     "tfft_set_faults": ([_P, ctypes.POINTER(tfft_fault), ctypes.c_int64], ctypes.c_int),
     "tfft_plan_info": ([_P, ctypes.POINTER(tfft_plan_desc)], ctypes.c_int),
+    "tfft_set_timing": ([_P, ctypes.c_int], ctypes.c_int),
+    "tfft_get_timings": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tfft_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "tfft_version": ([], ctypes.c_int),
 }
@@ -205,6 +207,17 @@ class Plan:
             arr[i] = tfft_fault(int(f["signal"]), int(f.get("pass_", 0)), int(f.get("stage", -1)),
                                 int(f["index"]), v.real, v.imag)
         _check(tfft_set_faults(self._h, arr, len(faults)), "tfft_set_faults")
+
+    def set_timing(self, enable: bool = True):
+        _check(tfft_set_timing(self._h, 1 if enable else 0), "tfft_set_timing")
+
+    def timings(self):
+        """(pass_ms[passes], correct_ms[passes]) of the last timed execution."""
+        a = (ctypes.c_double * 2)()
+        b = (ctypes.c_double * 2)()
+        _check(tfft_get_timings(self._h, a, b), "tfft_get_timings")
+        p = self.info()["passes"]
+        return list(a[:p]), list(b[:p])
 
     def report(self, cap: int | None = None):
         """(counts dict, [Record]) of the last execution; synchronises its stream."""

@@ -1,6 +1,6 @@
 """Build the HIP library ``libtfft.so`` in-tree with hipcc for gfx950.
 
-    python -m paper_2405_02520_amd.build [--resource-usage]
+    python paper_2405_02520_amd/build.py [--resource-usage]
 
 The two translation units are compiled in parallel and linked into a shared
 library next to this file.  Every HIP source is built with packed FP32

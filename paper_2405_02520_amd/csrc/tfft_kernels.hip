@@ -184,19 +184,40 @@ __device__ __forceinline__ cx<double> itw(const PassArgs &a, int64_t t) {
     return cmul(lo, hi);
 }
 
-template <typename R, int E>
-__device__ __noinline__ void apply_faults(cx<R> (&d)[E], const DevFault *F, int fh, int stage, int b, int j) {
+// Fault hook (test instrument): the register of this thread that a fault of
+// the group hits at `stage`, or m = -1.  Returned by value so that the
+// register array of the caller is never address-taken (it would be placed in
+// scratch memory).
+struct FaultHit {
+    int m;
+    double dre, dim;
+};
+
+__device__ __forceinline__ FaultHit find_fault(const DevFault *F, int fh, int stage, int b, int j) {
+    FaultHit h{-1, 0.0, 0.0};
     for (int f = fh; f >= 0; f = F[f].next) {
         const DevFault x = F[f];
         if (x.stage == stage && x.member == b && x.j == j) {
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                if (m == x.m) {
-                    d[m].re += R(x.dre);
-                    d[m].im += R(x.dim);
-                }
+            if (h.m < 0 || h.m == x.m) {
+                h.m = x.m;
+                h.dre += x.dre;
+                h.dim += x.dim;
             }
         }
+    }
+    return h;
+}
+
+template <typename R, int E>
+__device__ __forceinline__ void apply_faults(cx<R> (&d)[E], const DevFault *F, int fh, int stage, int b, int j) {
+    const FaultHit h = find_fault(F, fh, stage, b, j);
+    // every register takes an addend that is zero except at h.m: written as
+    // an add of a selected value (not a conditional update) so the compiler
+    // cannot turn it into an indexed store that would demote d[] to scratch
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        d[m].re += (m == h.m) ? R(h.dre) : R(0);
+        d[m].im += (m == h.m) ? R(h.dim) : R(0);
     }
 }
 
@@ -287,11 +308,15 @@ pass_kernel(PassArgs a) {
         for (int r = 0; r < rounds; ++r) {
             const int b = r * C + c;
             const MemberLoc L = member_loc<M, KIND, C>(a, g, b);
+            // offsets inside one signal are below N <= 2^24: 32-bit arithmetic
+            const cx<R> *src = in + L.in_off;
+            cx<R> *dst = out + L.out_off;
+            const uint32_t istr = (uint32_t)L.in_stride, ostr = (uint32_t)L.out_stride;
             cx<R> d[E];
 #pragma unroll
             for (int m = 0; m < E; ++m) {
                 d[m] = cx<R>{R(0), R(0)};
-                if (L.valid) d[m] = ldg(in + L.in_off + (int64_t)(j + T * m) * L.in_stride);
+                if (L.valid) d[m] = ldg(src + (uint32_t)(j + T * m) * istr);
             }
             if constexpr (FT) {
                 double lr = 0.0, li = 0.0;
@@ -411,16 +436,16 @@ pass_kernel(PassArgs a) {
                 for (int m = 0; m < E; ++m) lds[c * M + j + T * m] = d[m];
                 __syncthreads();
                 const int c2 = tid % C, j2 = tid / C;
-                const int64_t base = L.out_off - c + c2;  // rows of one tile share beta
+                cx<R> *base = dst - c + c2;  // rows of one tile share beta
                 if (L.valid) {
 #pragma unroll
-                    for (int m = 0; m < E; ++m) stg(out + base + (int64_t)(j2 + T * m) * a.n1, lds[c2 * M + j2 + T * m]);
+                    for (int m = 0; m < E; ++m) stg(base + (uint32_t)(j2 + T * m) * ostr, lds[c2 * M + j2 + T * m]);
                 }
                 __syncthreads();
             } else {
                 if (L.valid) {
 #pragma unroll
-                    for (int m = 0; m < E; ++m) stg(out + L.out_off + (int64_t)(j + T * m) * L.out_stride, d[m]);
+                    for (int m = 0; m < E; ++m) stg(dst + (uint32_t)(j + T * m) * ostr, d[m]);
                 }
             }
         }  // rounds

@@ -93,6 +93,10 @@ struct tfft_plan_s {
     int executed = 0;
     int last_mode = 0;
     int64_t nfaults = 0;
+    int timing = 0;              // record events around each launch
+    int timed_last = 0;          // the last execution was timed
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int launched_correct = 0;
 };
 
 namespace {
@@ -209,6 +213,8 @@ void free_plan(tfft_plan_s *p) {
     (void)hipFree(p->d_work);
     (void)hipFree(p->d_rep);
     (void)hipFree(p->d_recs);
+    for (auto &e : p->ev)
+        if (e) (void)hipEventDestroy(e);
     (void)hipSetDevice(cur);
     delete p;
 }
@@ -250,6 +256,8 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
     const int fp64 = p->dtype == TFFT_C128;
     const int ft = mode != TFFT_FT_OFF;
     if (launch_reset(p->d_rep, st) != hipSuccess) return TFFT_E_HIP;
+    const bool timed = p->timing != 0;
+    if (timed && hipEventRecord(p->ev[0], st) != hipSuccess) return TFFT_E_HIP;
     for (int i = 0; i < p->passes; ++i) {
         const PassPlan &P = p->pass[i];
         const bool last = i == p->passes - 1;
@@ -282,10 +290,14 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
         A.fault_head = P.d_fault_head;
         A.faults = P.d_faults;
         if (launch_pass(fp64, P.M, P.kind, ft, A, P.grid, st) != hipSuccess) return TFFT_E_HIP;
+        if (timed && hipEventRecord(p->ev[1 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
         if (mode == TFFT_FT_CORRECT) {
             if (launch_correct(fp64, P.M, P.kind, A, 64, st) != hipSuccess) return TFFT_E_HIP;
         }
+        if (timed && hipEventRecord(p->ev[2 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
     }
+    p->timed_last = timed ? 1 : 0;
+    p->launched_correct = mode == TFFT_FT_CORRECT;
     p->last_stream = st;
     p->executed = 1;
     p->last_mode = mode;
@@ -529,6 +541,34 @@ int tfft_set_faults(tfft_plan p, const tfft_fault *specs, int64_t n) {
         }
     }
     p->nfaults = n;
+    return TFFT_OK;
+}
+
+int tfft_set_timing(tfft_plan p, int enable) {
+    if (!p) return TFFT_E_INVALID;
+    Guard guard(p->device);
+    if (enable) {
+        for (auto &e : p->ev)
+            if (!e && hipEventCreate(&e) != hipSuccess) return TFFT_E_HIP;
+    }
+    p->timing = enable ? 1 : 0;
+    return TFFT_OK;
+}
+
+int tfft_get_timings(tfft_plan p, double *pass_ms, double *correct_ms) {
+    if (!p) return TFFT_E_INVALID;
+    if (!p->executed || !p->timed_last) return TFFT_E_STATE;
+    Guard guard(p->device);
+    if (hipEventSynchronize(p->ev[2 * p->passes]) != hipSuccess) return TFFT_E_HIP;
+    for (int i = 0; i < 2; ++i) {
+        float a = 0.f, b = 0.f;
+        if (i < p->passes) {
+            if (hipEventElapsedTime(&a, p->ev[2 * i], p->ev[2 * i + 1]) != hipSuccess) return TFFT_E_HIP;
+            if (hipEventElapsedTime(&b, p->ev[2 * i + 1], p->ev[2 * i + 2]) != hipSuccess) return TFFT_E_HIP;
+        }
+        if (pass_ms) pass_ms[i] = a;
+        if (correct_ms) correct_ms[i] = p->launched_correct ? b : 0.0;
+    }
     return TFFT_OK;
 }
 

@@ -31,7 +31,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ["tfft_plan_create", "tfft_plan_create_with", "tfft_plan_destroy", "tfft_exec_forward",
               "tfft_exec_inverse", "tfft_get_report", "tfft_set_faults", "tfft_plan_info",
-              "tfft_status_string", "tfft_version"]:
+              "tfft_status_string", "tfft_version", "tfft_set_timing", "tfft_get_timings"]:
         assert n in names
 
 
@@ -74,6 +74,8 @@ def test_null_plan_is_rejected(tf):
     assert tf.tfft_get_report(None, None, None, 0) == tf.E_INVALID
     assert tf.tfft_set_faults(None, None, 0) == tf.E_INVALID
     assert tf.tfft_plan_info(None, None) == tf.E_INVALID
+    assert tf.tfft_set_timing(None, 1) == tf.E_INVALID
+    assert tf.tfft_get_timings(None, None, None) == tf.E_INVALID
 
 
 def test_record_layouts_match_header(tf):
