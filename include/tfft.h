@@ -34,6 +34,7 @@ extern "C" {
 #endif
 
 #define TFFT_VERSION 1
+#define TFFT_MAX_PASSES 3
 
 typedef struct tfft_plan_s *tfft_plan;
 
@@ -87,13 +88,13 @@ typedef struct {
 typedef struct {
     int64_t n, batch;
     int32_t dtype, passes;
-    int32_t pass_len[2];       /* transform length of each pass, product = n          */
-    int32_t group[2];          /* checksum group size of each pass                    */
-    int32_t elems_per_thread[2];
-    int32_t tile_signals[2];   /* signals held in LDS at once by one workgroup         */
-    int32_t stages[2];
-    int32_t radices[2][8];     /* butterfly radix of each stage of each pass           */
-    int64_t groups[2];         /* checksum groups per pass                             */
+    int32_t pass_len[TFFT_MAX_PASSES];     /* transform length of each pass, product = n */
+    int32_t group[TFFT_MAX_PASSES];        /* checksum group size of each pass           */
+    int32_t elems_per_thread[TFFT_MAX_PASSES];
+    int32_t tile_signals[TFFT_MAX_PASSES]; /* sub-signals held in LDS by one workgroup   */
+    int32_t stages[TFFT_MAX_PASSES];
+    int32_t radices[TFFT_MAX_PASSES][8];   /* butterfly radix of each stage of each pass */
+    int64_t groups[TFFT_MAX_PASSES];       /* checksum groups per pass                   */
     size_t workspace_bytes;
     double kappa;
 } tfft_plan_desc;
@@ -112,7 +113,8 @@ typedef struct {
 /* One flagged group. */
 typedef struct {
     int64_t signal;   /* batch index of the affected signal (group's first signal if not located) */
-    int64_t sub;      /* two-pass plans: column (pass 0) or row (pass 1) of the located member; else 0 */
+    int64_t sub;      /* multi-pass plans: sub-transform of the located member inside the signal
+                         (see tfft_fault); one-pass plans: 0 */
     int64_t group;    /* checksum group index within the pass */
     int32_t pass;     /* 0-based pass */
     int32_t member;   /* located member within the group, -1 if none */
@@ -130,9 +132,12 @@ typedef struct {
  *   stage == -1: to final output value `index` of the pass (after the
  *               inter-pass twiddle, conjugation and scale), before the
  *               post-transform checksum.
- * For two-pass plans index = sub * pass_len + position, with sub the column
- * (pass 0) or row (pass 1); for one-pass plans index = position.  This models
- * a compute fault (paper Section II-A) inside the protected region. */
+ * For one-pass plans index = position.  For a plan of P passes with lengths
+ * M_1..M_P, pass p transforms N / M_p sub-signals of each signal and
+ * index = sub * M_p + position, where for p < P sub = o * S_p + i (block o of
+ * L_p = M_p...M_P elements, offset i < S_p = L_p / M_p inside the stride) and
+ * for the last pass sub is the output row r (outputs r + (N / M_P) k).  This
+ * models a compute fault (paper Section II-A) inside the protected region. */
 typedef struct {
     int64_t signal;
     int32_t pass;
@@ -142,10 +147,12 @@ typedef struct {
 } tfft_fault;
 
 /* Create a plan for `batch` transforms of length `n` (a power of two,
- * 2 <= n <= 2^24) of element type `dtype`.  Chooses one pass for n <= 4096 and
- * two passes (n = n1 * n2, Section IV-A.1) above; generates every twiddle and
+ * 2 <= n <= 2^24) of element type `dtype`.  Chooses one pass for n <= 2^12,
+ * two passes up to 2^16 and three above (n = M_1 M_2 [M_3], the tiled FFT of
+ * Section IV-A.1, last pass stored transposed); generates every twiddle and
  * checksum vector in binary64 on the host and rounds it once; allocates the
- * tables, the workspace (two-pass plans: n * batch elements) and the report.
+ * tables, the workspace (multi-pass plans: n * batch elements; three-pass
+ * plans also use the output buffer between passes) and the report.
  * *out receives the plan, or NULL on error.  E_INVALID for bad arguments,
  * E_NOMEM / E_HIP on allocation failure. */
 int tfft_plan_create(tfft_plan *out, int64_t n, int64_t batch, int dtype, uint32_t flags);
@@ -183,7 +190,8 @@ int tfft_plan_info(tfft_plan p, tfft_plan_desc *info);
  * each kernel launch; tfft_get_timings synchronises that stream and writes
  * the durations of the last execution in milliseconds: pass_ms[p] for the
  * transform kernel of pass p and correct_ms[p] for its correction launch
- * (0 when not launched); each array holds 2 entries, either may be NULL.
+ * (0 when not launched); each array holds TFFT_MAX_PASSES entries, either may
+ * be NULL.
  * E_STATE if timing was off for the last execution. */
 int tfft_set_timing(tfft_plan p, int enable);
 int tfft_get_timings(tfft_plan p, double *pass_ms, double *correct_ms);

@@ -43,12 +43,16 @@ class tfft_options(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 8)]
 
 
+MAX_PASSES = 3
+
+
 class tfft_plan_desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("batch", ctypes.c_int64), ("dtype", ctypes.c_int32),
-                ("passes", ctypes.c_int32), ("pass_len", ctypes.c_int32 * 2), ("group", ctypes.c_int32 * 2),
-                ("elems_per_thread", ctypes.c_int32 * 2), ("tile_signals", ctypes.c_int32 * 2),
-                ("stages", ctypes.c_int32 * 2), ("radices", (ctypes.c_int32 * 8) * 2),
-                ("groups", ctypes.c_int64 * 2), ("workspace_bytes", ctypes.c_size_t), ("kappa", ctypes.c_double)]
+                ("passes", ctypes.c_int32), ("pass_len", ctypes.c_int32 * MAX_PASSES),
+                ("group", ctypes.c_int32 * MAX_PASSES), ("elems_per_thread", ctypes.c_int32 * MAX_PASSES),
+                ("tile_signals", ctypes.c_int32 * MAX_PASSES), ("stages", ctypes.c_int32 * MAX_PASSES),
+                ("radices", (ctypes.c_int32 * 8) * MAX_PASSES), ("groups", ctypes.c_int64 * MAX_PASSES),
+                ("workspace_bytes", ctypes.c_size_t), ("kappa", ctypes.c_double)]
 
 
 class tfft_counts(ctypes.Structure):
@@ -213,8 +217,8 @@ class Plan:
 
     def timings(self):
         """(pass_ms[passes], correct_ms[passes]) of the last timed execution."""
-        a = (ctypes.c_double * 2)()
-        b = (ctypes.c_double * 2)()
+        a = (ctypes.c_double * MAX_PASSES)()
+        b = (ctypes.c_double * MAX_PASSES)()
         _check(tfft_get_timings(self._h, a, b), "tfft_get_timings")
         p = self.info()["passes"]
         return list(a[:p]), list(b[:p])

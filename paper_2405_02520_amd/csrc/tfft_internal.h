@@ -6,14 +6,17 @@
 
 namespace tfft {
 
-// Pass roles of the tiled FFT (TurboFFT Section IV-A.1).
-//  ROWS   one-pass plan: each signal is contiguous, output contiguous.
-//  COLS   first pass of a two-pass plan: length-n1 columns (stride n2) of each
-//         signal, multiplied by the inter-pass twiddle w_N^{k1 n2}, stored
-//         back in the same [n1][n2] layout into the workspace.
-//  ROWS_T second pass: length-n2 rows of the workspace, stored transposed,
-//         y[k1 + n1 k2].
-enum Kind { KIND_ROWS = 0, KIND_COLS = 1, KIND_ROWS_T = 2 };
+// Pass roles of the tiled FFT (TurboFFT Section IV-A.1).  A length-N signal
+// is split N = M_1 * ... * M_P (P <= 3); pass p transforms axis p.
+//  ROWS     one-pass plan: each signal is contiguous, output contiguous.
+//  STRIDED  pass p < P: within each block of L_p = M_p * ... * M_P elements,
+//           the M_p elements of axis p are S_p = L_p / M_p apart; the result
+//           is multiplied by the twiddle w_{L_p}^{k_p i} (i = position inside
+//           the stride) and stored back in place, in the same layout.
+//  LAST     pass P: contiguous rows of length M_P; the outputs are stored
+//           transposed, y[r + (N / M_P) k_P], r the digit-reversed row.
+enum Kind { KIND_ROWS = 0, KIND_STRIDED = 1, KIND_LAST = 2 };
+constexpr int kMaxPasses = 3;
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 constexpr int ipowc(int b, int e) { return e == 0 ? 1 : b * ipowc(b, e - 1); }
@@ -21,16 +24,18 @@ constexpr int ipowc(int b, int e) { return e == 0 ? 1 : b * ipowc(b, e - 1); }
 // ---------------------------------------------------------------- config
 // Elements held by one thread (the thread-level radix, Section IV-A.2).
 constexpr int cfg_E(int fp64, int M) { return M >= 8 ? 8 : M; }
-// Signals held in LDS at once by one workgroup (the tile).  A tile has at
-// most 256 threads (more only when one signal alone needs more) and at most
-// 64 KiB of LDS.
+// Signals held in LDS at once by one workgroup (the tile).  One-pass tiles
+// aim at 256 threads; multi-pass tiles are as wide as 512 threads and 64 KiB
+// of LDS allow (at most 32 signals), because the strided loads and the
+// transposed stores of those passes move C adjacent elements per row.
 constexpr int cfg_C(int fp64, int M, int kind) {
     const int E = cfg_E(fp64, M);
     const int T = M / E;
     const int S = fp64 ? 16 : 8;
-    int c = kind == KIND_ROWS ? 256 / (T > 0 ? T : 1) : 16;
-    if (c > 16) c = 16;
-    while (c > 1 && (c * T > 256 || c * M * S > 65536)) c /= 2;
+    int c = kind == KIND_ROWS ? 256 / (T > 0 ? T : 1) : 32;
+    if (kind == KIND_ROWS && c > 16) c = 16;
+    const int maxthr = kind == KIND_ROWS ? 256 : 512;
+    while (c > 1 && (c * T > maxthr || c * M * S > 65536)) c /= 2;
     return c < 1 ? 1 : c;
 }
 // Keep the stage twiddles / the checksum vector of a thread in registers
@@ -76,11 +81,17 @@ struct PassArgs {
     void *out;
     int64_t batch;      // B
     int64_t n;          // full transform length N
-    int32_t n1, n2;     // two-pass split N = n1 * n2 (one-pass: n1 = N, n2 = 1)
+    int64_t L;          // STRIDED: block length L_p
+    int32_t S;          // STRIDED: stride S_p of the transform axis
+    int32_t O;          // STRIDED: blocks per signal (N / L_p)
+    int64_t rows;       // LAST: rows per signal, N / M_P (output stride)
+    int32_t m1, m2;     // LAST: row r comes from block (r mod m1) * m2 + r / m1
     int32_t G;          // members per checksum group
-    int32_t rb;         // two-pass: batch entries per group (G = C * rb)
-    int64_t n_strips;   // two-pass: tiles of C sub-signals per batch entry
+    int32_t rb;         // multi-pass: outer units per group (G = C * rb)
+    int64_t n_strips;   // multi-pass: tiles of C sub-signals per outer unit
+    int64_t n_outer;    // multi-pass: outer units (B * O for STRIDED, B for LAST)
     int64_t n_groups;   // groups of this launch
+    int64_t tw_scale;   // STRIDED: w_{L}^t = w_N^{t * tw_scale}
     int32_t conj_in, conj_out;
     double out_scale;   // applied to the final values when != 1
     const double *cvec; // [2M] checksum vector c of this pass and direction (fp64)
@@ -101,6 +112,5 @@ struct PassArgs {
 hipError_t launch_pass(int fp64, int M, int kind, int ft, const PassArgs &a, int grid, hipStream_t st);
 hipError_t launch_correct(int fp64, int M, int kind, const PassArgs &a, int grid, hipStream_t st);
 hipError_t launch_reset(DevReport *rep, hipStream_t st);
-int pass_max_grid(int fp64, int M, int kind, int ft);
 
 }  // namespace tfft

@@ -139,8 +139,12 @@ struct Stages {
 };
 
 // ----------------------------------------------------------- addressing
+// Where member b of group g lives.  Offsets inside one signal are below
+// N <= 2^24, so the in-signal part is 32-bit.
 struct MemberLoc {
-    int64_t in_off, in_stride, out_off, out_stride, sub;
+    int64_t in_off, out_off;
+    uint32_t in_stride, out_stride;
+    int64_t tw_i;  // STRIDED: position inside the stride (twiddle exponent factor)
     bool valid;
 };
 
@@ -151,29 +155,49 @@ __device__ __forceinline__ MemberLoc member_loc(const PassArgs &a, int64_t g, in
         const int64_t s = g * a.G + b;
         L.valid = s < a.batch;
         L.in_off = s * M;
-        L.in_stride = 1;
         L.out_off = s * M;
+        L.in_stride = 1;
         L.out_stride = 1;
-        L.sub = 0;
+        L.tw_i = 0;
     } else {
         const int64_t strip = g % a.n_strips;
-        const int64_t beta = (g / a.n_strips) * a.rb + b / C;
-        const int64_t sub = strip * C + b % C;
-        L.valid = beta < a.batch;
-        L.sub = sub;
-        if constexpr (KIND == KIND_COLS) {
-            L.in_off = beta * a.n + sub;
-            L.in_stride = a.n2;
+        const int64_t u = (g / a.n_strips) * a.rb + b / C;  // outer unit
+        const int64_t r = strip * C + b % C;                 // sub-signal inside the unit
+        L.valid = u < a.n_outer;
+        if constexpr (KIND == KIND_STRIDED) {
+            const int64_t beta = u / a.O, o = u % a.O;
+            L.in_off = beta * a.n + o * a.L + r;
             L.out_off = L.in_off;
-            L.out_stride = a.n2;
+            L.in_stride = (uint32_t)a.S;
+            L.out_stride = (uint32_t)a.S;
+            L.tw_i = r;
         } else {
-            L.in_off = beta * a.n + sub * a.n2;
+            const int64_t o = (r % a.m1) * a.m2 + r / a.m1;
+            L.in_off = u * a.n + o * M;
+            L.out_off = u * a.n + r;
             L.in_stride = 1;
-            L.out_off = beta * a.n + sub;
-            L.out_stride = a.n1;
+            L.out_stride = (uint32_t)a.rows;
+            L.tw_i = 0;
         }
     }
     return L;
+}
+
+// LDS element index of position `pos` of tile slot `slot`, XOR-swizzled
+// inside each 256-byte bank row so that the Stockham scatter writes, the
+// strided reads and the transposed-store re-map hit distinct banks.  The
+// swizzle is a unit-triangular map over GF(2) of the low bits: a bijection
+// on every power-of-two tile.
+template <typename R, int M, int C, int KIND>
+__device__ __forceinline__ int lds_index(int slot, int pos) {
+    constexpr int RE = 256 / (2 * (int)sizeof(R));  // elements per bank row
+    if constexpr (KIND == KIND_STRIDED) {
+        const int L = pos * C + slot;
+        return L ^ ((L >> 3) & (RE - 1));
+    } else {
+        const int L = slot * M + pos;
+        return L ^ (((L >> 3) ^ (L >> 7)) & (RE - 1));
+    }
 }
 
 // w_N^t from the two-level fp64 table.
@@ -248,7 +272,7 @@ pass_kernel(PassArgs a) {
 
     const int tid = threadIdx.x;
     int c, j;
-    if constexpr (KIND == KIND_COLS) {
+    if constexpr (KIND == KIND_STRIDED) {
         c = tid % C;
         j = tid / C;
     } else {
@@ -258,11 +282,7 @@ pass_kernel(PassArgs a) {
     const cx<R> *in = reinterpret_cast<const cx<R> *>(a.in);
     cx<R> *out = reinterpret_cast<cx<R> *>(a.out);
 
-    // LDS index of element `pos` of tile slot `slot`
-    auto lidx = [](int slot, int pos) -> int {
-        if constexpr (KIND == KIND_COLS) return pos * C + slot;
-        else return slot * M + pos;
-    };
+    auto lidx = [](int slot, int pos) -> int { return lds_index<R, M, C, KIND>(slot, pos); };
 
     // Stage twiddles w_{NS*RAD}^{(i mod NS) q} (from the table of w_M^t) and
     // the pre-transform checksum vector at positions j + T m: either kept in
@@ -313,10 +333,12 @@ pass_kernel(PassArgs a) {
             cx<R> *dst = out + L.out_off;
             const uint32_t istr = (uint32_t)L.in_stride, ostr = (uint32_t)L.out_stride;
             cx<R> d[E];
+            if (L.valid) {
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                d[m] = cx<R>{R(0), R(0)};
-                if (L.valid) d[m] = ldg(src + (uint32_t)(j + T * m) * istr);
+                for (int m = 0; m < E; ++m) d[m] = ldg(src + (uint32_t)(j + T * m) * istr);
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; ++m) d[m] = cx<R>{R(0), R(0)};
             }
             if constexpr (FT) {
                 double lr = 0.0, li = 0.0;
@@ -378,9 +400,10 @@ pass_kernel(PassArgs a) {
             // inter-pass twiddle (COLS): w_N^{k sub} = A B^m with A = w_N^{j sub},
             // B = w_N^{T sub}, products in fp64, each rounded once
             cx<double> twA{1.0, 0.0}, twB{1.0, 0.0};
-            if constexpr (KIND == KIND_COLS) {
-                twA = itw(a, (int64_t(j) * L.sub) % a.n);
-                twB = itw(a, (int64_t(T) * L.sub) % a.n);
+            if constexpr (KIND == KIND_STRIDED) {
+                // w_L^{k i} = w_N^{k i N/L}
+                twA = itw(a, (int64_t(j) * L.tw_i * a.tw_scale) % a.n);
+                twB = itw(a, (int64_t(T) * L.tw_i * a.tw_scale) % a.n);
                 cx<double> P = twA;
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
@@ -408,7 +431,7 @@ pass_kernel(PassArgs a) {
                 for (int m = 0; m < E; ++m) {
                     const int cls = ((T % 3) * m) % 3;
                     double vr = double(d[m].re), vi = double(d[m].im);
-                    if constexpr (KIND == KIND_COLS) {
+                    if constexpr (KIND == KIND_STRIDED) {
                         // e' = e conj(applied twiddle); applied = P (forward) or conj(P) (inverse)
                         const double pr = P.re, pi = a.conj_out ? -P.im : P.im;
                         const double ur = vr * pr + vi * pi, ui = vi * pr - vr * pi;
@@ -429,17 +452,17 @@ pass_kernel(PassArgs a) {
                 D2r += w2 * rr;
                 D2i += w2 * ri;
             }
-            if constexpr (KIND == KIND_ROWS_T) {
+            if constexpr (KIND == KIND_LAST) {
                 // transposed store: re-map through LDS so that lanes run along
-                // the C adjacent rows of the tile
+                // the C adjacent output rows of the tile
 #pragma unroll
-                for (int m = 0; m < E; ++m) lds[c * M + j + T * m] = d[m];
+                for (int m = 0; m < E; ++m) lds[lidx(c, j + T * m)] = d[m];
                 __syncthreads();
                 const int c2 = tid % C, j2 = tid / C;
-                cx<R> *base = dst - c + c2;  // rows of one tile share beta
+                cx<R> *base = dst - c + c2;  // rows of one tile share the batch entry
                 if (L.valid) {
 #pragma unroll
-                    for (int m = 0; m < E; ++m) stg(base + (uint32_t)(j2 + T * m) * ostr, lds[c2 * M + j2 + T * m]);
+                    for (int m = 0; m < E; ++m) stg(base + (uint32_t)(j2 + T * m) * ostr, lds[lidx(c2, j2 + T * m)]);
                 }
                 __syncthreads();
             } else {
@@ -537,8 +560,8 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
 
         // applied output twiddle of member loc at output k (1 outside COLS)
         auto applied = [&](const MemberLoc &L, int k) -> cx<double> {
-            if constexpr (KIND == KIND_COLS) {
-                cx<double> w = itw(a, (int64_t(k) * L.sub) % a.n);
+            if constexpr (KIND == KIND_STRIDED) {
+                cx<double> w = itw(a, (int64_t(k) * L.tw_i * a.tw_scale) % a.n);
                 if (a.conj_out) w.im = -w.im;
                 return w;
             } else {
@@ -546,11 +569,11 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
             }
         };
         auto load_in = [&](const MemberLoc &L, int n) -> cx<double> {
-            const cx<R> x = ldg(in + L.in_off + (int64_t)n * L.in_stride);
+            const cx<R> x = ldg(in + L.in_off + (uint32_t)n * L.in_stride);
             return {double(x.re), double(x.im)};
         };
         auto load_out = [&](const MemberLoc &L, int k) -> cx<double> {
-            const cx<R> y = ldg(out + L.out_off + (int64_t)k * L.out_stride);
+            const cx<R> y = ldg(out + L.out_off + (uint32_t)k * L.out_stride);
             return {double(y.re), double(y.im)};
         };
         auto ek = [](int k) -> cx<double> {
@@ -638,7 +661,7 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
                     if (L.valid) acc = csub(acc, cmulconj(load_out(L, k), applied(L, k)));
                 }
                 const cx<double> y = cmul(acc, applied(Lj, k));
-                stg(out + Lj.out_off + (int64_t)k * Lj.out_stride, cx<R>{R(y.re), R(y.im)});
+                stg(out + Lj.out_off + (uint32_t)k * Lj.out_stride, cx<R>{R(y.re), R(y.im)});
             }
             action = 2;
         } else {
@@ -689,9 +712,9 @@ static hipError_t launch_kind(int ft, const PassArgs &a, int grid, hipStream_t s
 template <typename R, int M>
 static hipError_t launch_m(int kind, int ft, const PassArgs &a, int grid, hipStream_t st) {
     if (kind == KIND_ROWS) return launch_kind<R, M, KIND_ROWS>(ft, a, grid, st);
-    if constexpr (M >= 64) {
-        if (kind == KIND_COLS) return launch_kind<R, M, KIND_COLS>(ft, a, grid, st);
-        if (kind == KIND_ROWS_T) return launch_kind<R, M, KIND_ROWS_T>(ft, a, grid, st);
+    if constexpr (M >= 16 && M <= 1024) {
+        if (kind == KIND_STRIDED) return launch_kind<R, M, KIND_STRIDED>(ft, a, grid, st);
+        if (kind == KIND_LAST) return launch_kind<R, M, KIND_LAST>(ft, a, grid, st);
     }
     return hipErrorInvalidValue;
 }
@@ -702,13 +725,13 @@ static hipError_t correct_m(int kind, const PassArgs &a, int grid, hipStream_t s
         hipLaunchKernelGGL((correct_kernel<R, M, KIND_ROWS>), dim3(grid), dim3(kCorrThreads), 0, st, a);
         return hipGetLastError();
     }
-    if constexpr (M >= 64) {
-        if (kind == KIND_COLS) {
-            hipLaunchKernelGGL((correct_kernel<R, M, KIND_COLS>), dim3(grid), dim3(kCorrThreads), 0, st, a);
+    if constexpr (M >= 16 && M <= 1024) {
+        if (kind == KIND_STRIDED) {
+            hipLaunchKernelGGL((correct_kernel<R, M, KIND_STRIDED>), dim3(grid), dim3(kCorrThreads), 0, st, a);
             return hipGetLastError();
         }
-        if (kind == KIND_ROWS_T) {
-            hipLaunchKernelGGL((correct_kernel<R, M, KIND_ROWS_T>), dim3(grid), dim3(kCorrThreads), 0, st, a);
+        if (kind == KIND_LAST) {
+            hipLaunchKernelGGL((correct_kernel<R, M, KIND_LAST>), dim3(grid), dim3(kCorrThreads), 0, st, a);
             return hipGetLastError();
         }
     }

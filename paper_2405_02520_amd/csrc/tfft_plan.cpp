@@ -59,7 +59,9 @@ cd unit_root(int64_t t, int64_t n) {
 
 struct PassPlan {
     int M = 0, kind = 0, E = 0, C = 0, G = 0, rb = 1, stages = 0;
-    int64_t n_strips = 1, n_groups = 0;
+    int64_t n_strips = 1, n_groups = 0, n_outer = 0;
+    int64_t L = 0, rows = 0, tw_scale = 1;
+    int S = 1, O = 1, m1 = 1, m2 = 1;
     int grid = 0;
     void *d_stw = nullptr;       // element-type stage twiddles
     double *d_stw64 = nullptr;   // fp64 stage twiddles
@@ -80,8 +82,8 @@ struct tfft_plan_s {
     uint32_t flags = 0;
     double kappa = 16.0;
     int passes = 0;
-    int n1 = 0, n2 = 0;
-    PassPlan pass[2];
+    int lens[kMaxPasses] = {0, 0, 0};
+    PassPlan pass[kMaxPasses];
     double *d_itw_lo = nullptr, *d_itw_hi = nullptr;
     int itw_bits = 0;
     void *d_work = nullptr;
@@ -95,7 +97,7 @@ struct tfft_plan_s {
     int64_t nfaults = 0;
     int timing = 0;              // record events around each launch
     int timed_last = 0;          // the last execution was timed
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[2 * kMaxPasses + 1] = {};
     int launched_correct = 0;
 };
 
@@ -158,13 +160,30 @@ int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser) {
         P.G = G0;
         P.rb = 1;
         P.n_strips = 1;
+        P.n_outer = p->batch;
         P.n_groups = (p->batch + P.G - 1) / P.G;
     } else {
-        const int64_t n_sub = kind == KIND_COLS ? p->n2 : p->n1;
-        P.rb = (int)std::max<int64_t>(1, std::min<int64_t>(std::max(1, G0 / P.C), p->batch));
+        int64_t n_sub;  // sub-signals per outer unit
+        if (kind == KIND_STRIDED) {
+            P.L = 1;
+            for (int q = idx; q < p->passes; ++q) P.L *= p->lens[q];
+            P.S = (int)(P.L / M);
+            P.O = (int)(p->n / P.L);
+            P.tw_scale = p->n / P.L;
+            P.n_outer = p->batch * P.O;
+            n_sub = P.S;
+        } else {
+            P.rows = p->n / M;
+            P.m1 = p->lens[0];
+            P.m2 = p->passes == 3 ? p->lens[1] : 1;
+            P.n_outer = p->batch;
+            n_sub = P.rows;
+        }
+        if (n_sub % P.C != 0) return TFFT_E_UNSUPPORTED;
+        P.rb = (int)std::max<int64_t>(1, std::min<int64_t>(std::max(1, G0 / P.C), P.n_outer));
         P.G = P.C * P.rb;
         P.n_strips = n_sub / P.C;
-        P.n_groups = P.n_strips * ((p->batch + P.rb - 1) / P.rb);
+        P.n_groups = P.n_strips * ((P.n_outer + P.rb - 1) / P.rb);
     }
     int64_t grid = std::min<int64_t>(P.n_groups, 2048);
     if (grid >= 8) grid = (grid + 7) / 8 * 8;
@@ -263,12 +282,29 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
         const bool last = i == p->passes - 1;
         PassArgs A;
         std::memset(&A, 0, sizeof(A));
-        A.in = i == 0 ? d_in : p->d_work;
-        A.out = last ? d_out : p->d_work;
+        // every pass reads a buffer it does not write, so a flagged group can
+        // re-read its inputs: 1 pass in->out; 2 passes in->work->out;
+        // 3 passes in->out->work->out (out holds the pass-1 result meanwhile)
+        if (p->passes == 1) {
+            A.in = d_in;
+            A.out = d_out;
+        } else if (p->passes == 2) {
+            A.in = i == 0 ? d_in : p->d_work;
+            A.out = i == 0 ? p->d_work : d_out;
+        } else {
+            A.in = i == 0 ? d_in : (i == 1 ? (const void *)d_out : p->d_work);
+            A.out = i == 1 ? p->d_work : d_out;
+        }
         A.batch = p->batch;
         A.n = p->n;
-        A.n1 = p->passes == 1 ? (int32_t)p->n : p->n1;
-        A.n2 = p->passes == 1 ? 1 : p->n2;
+        A.L = P.L;
+        A.S = P.S;
+        A.O = P.O;
+        A.rows = P.rows;
+        A.m1 = P.m1;
+        A.m2 = P.m2;
+        A.tw_scale = P.tw_scale;
+        A.n_outer = P.n_outer;
         A.G = P.G;
         A.rb = P.rb;
         A.n_strips = P.n_strips;
@@ -346,41 +382,49 @@ int tfft_plan_create_with(tfft_plan *out, int64_t n, int64_t batch, int dtype, c
     p->kappa = (opt && opt->kappa > 0) ? opt->kappa : 16.0;
     const int k = ilog2_64(n);
     int rc = TFFT_OK;
-    if (n <= 4096) {
+    // one pass up to 2^12; two passes of at most 2^8 each up to 2^16; three
+    // passes above, the shortest first (tiles of the strided passes then hold
+    // >= 16 adjacent sub-signals, i.e. >= 128-byte segments per row)
+    if (k <= 12) {
         p->passes = 1;
-        p->n1 = (int)n;
-        p->n2 = 1;
-        rc = build_pass(p, 0, (int)n, KIND_ROWS, Guser);
-    } else {
+        p->lens[0] = (int)n;
+    } else if (k <= 16) {
         p->passes = 2;
-        const int k1 = k / 2, k2 = k - k1;
-        p->n1 = 1 << k1;
-        p->n2 = 1 << k2;
-        rc = build_pass(p, 0, p->n1, KIND_COLS, Guser);
-        if (rc == TFFT_OK) rc = build_pass(p, 1, p->n2, KIND_ROWS_T, Guser);
+        p->lens[0] = 1 << (k / 2);
+        p->lens[1] = 1 << (k - k / 2);
+    } else {
+        p->passes = 3;
+        const int a = k / 3, b = (k - a) / 2, c = k - a - b;
+        p->lens[0] = 1 << a;
+        p->lens[1] = 1 << b;
+        p->lens[2] = 1 << c;
+    }
+    for (int i = 0; i < p->passes && rc == TFFT_OK; ++i) {
+        const int kind = p->passes == 1 ? KIND_ROWS : (i == p->passes - 1 ? KIND_LAST : KIND_STRIDED);
+        rc = build_pass(p, i, p->lens[i], kind, Guser);
+    }
+    if (rc == TFFT_OK && p->passes > 1) {
+        // w_N^t = lo[t mod 2^b] * hi[t >> b]
+        p->itw_bits = (k + 1) / 2;
+        const int64_t nlo = int64_t(1) << p->itw_bits, nhi = n >> p->itw_bits;
+        std::vector<double> lo(2 * (size_t)nlo), hi(2 * (size_t)nhi);
+        for (int64_t t = 0; t < nlo; ++t) {
+            const cd w = unit_root(t, n);
+            lo[2 * t] = w.real();
+            lo[2 * t + 1] = w.imag();
+        }
+        for (int64_t t = 0; t < nhi; ++t) {
+            const cd w = unit_root(t << p->itw_bits, n);
+            hi[2 * t] = w.real();
+            hi[2 * t + 1] = w.imag();
+        }
+        rc = upload(&p->d_itw_lo, lo);
+        if (rc == TFFT_OK) rc = upload(&p->d_itw_hi, hi);
         if (rc == TFFT_OK) {
-            // w_N^t = lo[t mod 2^b] * hi[t >> b]
-            p->itw_bits = (k + 1) / 2;
-            const int64_t nlo = int64_t(1) << p->itw_bits, nhi = n >> p->itw_bits;
-            std::vector<double> lo(2 * (size_t)nlo), hi(2 * (size_t)nhi);
-            for (int64_t t = 0; t < nlo; ++t) {
-                const cd w = unit_root(t, n);
-                lo[2 * t] = w.real();
-                lo[2 * t + 1] = w.imag();
-            }
-            for (int64_t t = 0; t < nhi; ++t) {
-                const cd w = unit_root(t << p->itw_bits, n);
-                hi[2 * t] = w.real();
-                hi[2 * t + 1] = w.imag();
-            }
-            rc = upload(&p->d_itw_lo, lo);
-            if (rc == TFFT_OK) rc = upload(&p->d_itw_hi, hi);
-            if (rc == TFFT_OK) {
-                p->work_bytes = (size_t)n * (size_t)batch * esz;
-                if (hipMalloc(&p->d_work, p->work_bytes) != hipSuccess) {
-                    p->d_work = nullptr;
-                    rc = TFFT_E_NOMEM;
-                }
+            p->work_bytes = (size_t)n * (size_t)batch * esz;
+            if (hipMalloc(&p->d_work, p->work_bytes) != hipSuccess) {
+                p->d_work = nullptr;
+                rc = TFFT_E_NOMEM;
             }
         }
     }
@@ -458,9 +502,15 @@ int tfft_get_report(tfft_plan p, tfft_counts *counts, tfft_record *recs, int64_t
             r.signal = d.group * P.G + mem;
             r.sub = 0;
         } else {
-            const int64_t strip = d.group % P.n_strips, bblock = d.group / P.n_strips;
-            r.signal = bblock * P.rb + mem / P.C;
-            r.sub = strip * P.C + mem % P.C;
+            const int64_t strip = d.group % P.n_strips, ublk = d.group / P.n_strips;
+            const int64_t u = ublk * P.rb + mem / P.C, i = strip * P.C + mem % P.C;
+            if (P.kind == KIND_STRIDED) {
+                r.signal = u / P.O;
+                r.sub = (u % P.O) * P.S + i;
+            } else {
+                r.signal = u;
+                r.sub = i;
+            }
         }
         r.group = d.group;
         r.pass = d.pass;
@@ -500,9 +550,16 @@ int tfft_set_faults(tfft_plan p, const tfft_fault *specs, int64_t n) {
         } else {
             const int64_t sub = s.index / M;
             pos = s.index % M;
-            const int64_t strip = sub / P.C, bblock = s.signal / P.rb;
-            g = bblock * P.n_strips + strip;
-            b = (int)((s.signal % P.rb) * P.C + sub % P.C);
+            int64_t u, i;
+            if (P.kind == KIND_STRIDED) {
+                u = s.signal * P.O + sub / P.S;
+                i = sub % P.S;
+            } else {
+                u = s.signal;
+                i = sub;
+            }
+            g = (u / P.rb) * P.n_strips + i / P.C;
+            b = (int)((u % P.rb) * P.C + i % P.C);
         }
         DevFault d;
         std::memset(&d, 0, sizeof(d));
@@ -560,7 +617,7 @@ int tfft_get_timings(tfft_plan p, double *pass_ms, double *correct_ms) {
     if (!p->executed || !p->timed_last) return TFFT_E_STATE;
     Guard guard(p->device);
     if (hipEventSynchronize(p->ev[2 * p->passes]) != hipSuccess) return TFFT_E_HIP;
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kMaxPasses; ++i) {
         float a = 0.f, b = 0.f;
         if (i < p->passes) {
             if (hipEventElapsedTime(&a, p->ev[2 * i], p->ev[2 * i + 1]) != hipSuccess) return TFFT_E_HIP;

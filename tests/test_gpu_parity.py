@@ -75,13 +75,13 @@ def test_single_pass_inverse(tf, dtype, log2n):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("log2n,B", [(13, 5), (14, 3), (16, 3), (18, 2), (20, 2), (24, 1)])
+@pytest.mark.parametrize("log2n,B", [(13, 5), (14, 3), (16, 3), (17, 3), (18, 2), (20, 2), (21, 1), (24, 1)])
 @pytest.mark.parametrize("inverse", [False, True])
-def test_two_pass(tf, dtype, log2n, B, inverse):
+def test_multi_pass(tf, dtype, log2n, B, inverse):
     n = 1 << log2n
     x = inputs.uniform(3000 + log2n, B, n, NPDT[dtype])
     y, counts, recs, plan = run(tf, x, dtype, inverse=inverse)
-    assert plan.info()["passes"] == 2
+    assert plan.info()["passes"] == (2 if log2n <= 16 else 3)
     assert oracle.rel_l2(y, reference(x, inverse)) <= TOL[dtype]
     assert counts["detected"] == 0, recs
 
@@ -172,24 +172,30 @@ def test_every_stage_every_member(tf, dtype, log2n):
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("inverse", [False, True])
-def test_two_pass_faults(tf, dtype, inverse):
-    n, B = 1 << 16, 4
-    x = inputs.uniform(500, B, n, NPDT[dtype])
+@pytest.mark.parametrize("log2n,B", [(16, 4), (18, 3)])
+def test_multi_pass_faults(tf, dtype, inverse, log2n, B):
+    """A fault after every stage of every pass, and on the final values of
+    every pass, in a random signal and element: detected in that pass and
+    corrected.  Magnitude: the RMS of the values at the end of the pass."""
+    n = 1 << log2n
+    x = inputs.uniform(500 + log2n, B, n, NPDT[dtype])
     plan = tf.Plan(n, B, dtype)
     info = plan.info()
     ref = reference(x, inverse)
-    rng = inputs.fault_rng(500)
-    for p in range(2):
+    rng = inputs.fault_rng(500 + log2n)
+    for p in range(info["passes"]):
+        done = math.prod(info["pass_len"][: p + 1])
         for stage in range(-1, info["stages"][p]):
             sig = int(rng.integers(B))
             idx = int(rng.integers(n))
-            mag = math.sqrt(2 * info["pass_len"][p] / 3) * (1 if p == 0 else math.sqrt(info["pass_len"][0]))
-            if inverse and p == 1 and stage == -1:
+            mag = math.sqrt(2 * done / 3)
+            if inverse and p == info["passes"] - 1 and stage == -1:
                 mag /= n  # final values of the inverse carry the 1/N
             fault = [dict(signal=sig, pass_=p, stage=stage, index=idx, value=mag * (0.6 - 0.8j))]
             y, counts, recs, _ = run(tf, x, dtype, inverse=inverse, faults=fault, plan=plan)
             assert counts["detected"] == 1 and counts["corrected"] == 1, (p, stage, counts, recs)
             assert recs[0].signal == sig and recs[0].pass_ == p
+            assert recs[0].sub == idx // info["pass_len"][p]
             assert oracle.rel_l2(y, ref) <= TOL[dtype], (p, stage)
 
 
