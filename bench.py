@@ -44,6 +44,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FT off / faulty overhead runs")
     ap.add_argument("--extra-reps", type=int, default=5)
+    ap.add_argument("--no-fault-runs", action="store_true", help="in the extras, skip the runs with injected faults")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="LOG2_BYTES",
+                    help="only run a plain device-to-device copy of 2^LOG2_BYTES bytes (the reference kernel "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_LOG2"),
+                    help="turn two rocprofv3 --pmc output directories (FETCH_SIZE, WRITE_SIZE) of a run that "
+                         "included the copy calibration into profiles/pmc_traffic.json and print a summary")
+    ap.add_argument("--ft", default="correct", choices=["off", "detect", "correct"],
+                    help="fault-tolerance mode of the timed workload (the headline uses correct)")
     return ap.parse_args()
 
 
@@ -89,8 +98,70 @@ def pmc_traffic(kernel_key):
         return None
 
 
+def copy_calibration(log2_bytes):
+    import torch
+
+    n = 1 << log2_bytes
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "launches": 3}), flush=True)
+
+
+def summarize_pmc(fetch_dir, write_dir, copy_log2, label_dt, label_k):
+    """Per-launch HBM traffic of each pass kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE: KiB per dispatch), each scaled by what the same
+    counter reads for a plain copy of known size."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        rows = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                rows.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return rows
+    copy_bytes = 1 << int(copy_log2)
+    fetch, write = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
+
+    def copy_kib(rows):
+        cands = [v for k, v in rows.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+        vals = [x for v in cands for x in v if x * 1024 > 0.5 * copy_bytes]
+        return sorted(vals)[len(vals) // 2] if vals else None
+    cf, cw = copy_kib(fetch), copy_kib(write)
+    sf = copy_bytes / (cf * 1024) if cf else None
+    sw = copy_bytes / (cw * 1024) if cw else None
+    src = os.path.join(ROOT, "paper_2405_02520_amd", "csrc", "tfft_kernels.hip")
+    out = {"kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+           "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": sf, "write_scale": sw, "entries": {}}
+    lines = [f"copy of {copy_bytes} B: FETCH_SIZE {cf} KiB, WRITE_SIZE {cw} KiB -> scale {sf}, {sw}"]
+    label = f"{label_dt}_k{label_k}"
+    for name in sorted(set(fetch) & set(write)):
+        if "pass_kernel" not in name:
+            continue
+        f = sorted(fetch[name])[len(fetch[name]) // 2] * 1024 * (sf or 1.0)
+        w = sorted(write[name])[len(write[name]) // 2] * 1024 * (sw or 1.0)
+        out["entries"][f"{label} {name}"] = {"fetch_bytes": f, "write_bytes": w, "traffic_bytes": f + w}
+        lines.append(f"{label} {name}: fetch {f / 2**30:.3f} GiB, write {w / 2**30:.3f} GiB per launch")
+    with open(os.path.join(ROOT, "profiles", "pmc_traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("\n".join(lines))
+
+
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, args.dtypes, args.kmin)
+        return
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; a batched FFT shards on the batch axis with no "
               "exchange (see DESIGN.md).  Run with --gpus 1.", file=sys.stderr)
@@ -134,13 +205,13 @@ def main():
 
     def step():
         for key in sizes:
-            plans[key].forward(xs[key], out=ys[key], ft_mode="correct", stream=stream)
+            plans[key].forward(xs[key], out=ys[key], ft_mode=args.ft, stream=stream)
 
     # warm-up; the first warm-up step also checks Parseval on every size
     sanity = {}
     for w in range(max(1, args.warmup)):
         for key in sizes:
-            plans[key].forward(xs[key], out=ys[key], ft_mode="correct", stream=stream)
+            plans[key].forward(xs[key], out=ys[key], ft_mode=args.ft, stream=stream)
             if w == 0:
                 dt, k = key
                 x, y = xs[key], ys[key]
@@ -192,17 +263,22 @@ def main():
         }
         info = plans[(dt, k)].info()
         for i, v in enumerate(pass_ms):
-            kind = "rows" if passes == 1 else ("cols" if i == 0 else "rows_t")
+            kind = "rows" if passes == 1 else ("last" if i == passes - 1 else "strided")
             cand = (v * len(rows), dt, k, i, kind, info["pass_len"][i], algo, v)
             if dom is None or cand[0] > dom[0]:
                 dom = cand
     _, ddt, dk, dpass, dkind, dM, dalgo, dms = dom
     achieved = dalgo / (dms * 1e-3) / 1e9
-    kernel_key = f"pass_kernel<{'float' if ddt == 'c64' else 'double'},{dM},{dkind},FT> {ddt} k={dk} pass={dpass}"
+    kind_code = {"rows": 0, "strided": 1, "last": 2}[dkind]
+    kernel_key = (f"{ddt}_k{dk} void tfft::pass_kernel<{'float' if ddt == 'c64' else 'double'}, {dM}, {kind_code}, "
+                  f"{'false' if args.ft == 'off' else 'true'}>(tfft::PassArgs)")
     tr = pmc_traffic(kernel_key)
+    if tr is not None:
+        tr = tr["traffic_bytes"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
-                "kernel": kernel_key, "algorithmic_bytes_per_launch": int(dalgo), "avg_launch_ms": round(dms, 4)}
+                "kernel": kernel_key, "pass": dpass, "algorithmic_bytes_per_launch": int(dalgo),
+                "avg_launch_ms": round(dms, 4)}
 
     # checksum overhead (same kernels, FT off) and cost of injected faults
     extras = {}
@@ -235,10 +311,14 @@ def main():
                 plen = info["pass_len"][0] if ps == 0 else n
                 faults.append(dict(signal=sig, pass_=ps, stage=-1, index=int(rng.integers(n)),
                                    value=math.sqrt(2.0 * plen / 3.0) * complex(0.6, -0.8)))
-            p.set_faults(faults)
-            t_fault = timed("correct")
-            c, recs = p.report()
-            p.set_faults([])
+            if args.no_fault_runs:
+                t_fault, c = float("nan"), {"corrected": 0, "detected": 0}
+                nf = 0
+            else:
+                p.set_faults(faults)
+                t_fault = timed("correct")
+                c, recs = p.report()
+                p.set_faults([])
             extras[f"{dt}_k{k}"] = {
                 "ms_ft_off": round(t_off, 4), "ms_ft_on": round(t_on, 4), "ms_ft_on_faulty": round(t_fault, 4),
                 "ft_overhead_pct": round((t_on / t_off - 1) * 100, 2),

@@ -34,26 +34,32 @@ def _compile(src: str, obj: str, extra: list[str]) -> str:
     return r.stderr
 
 
-def build(resource_usage: bool = False, verbose: bool = False) -> str:
-    objdir = os.path.join(HERE, "_build")
+def build(resource_usage: bool = False, verbose: bool = False, defines=(), lib: str | None = None) -> str:
+    """Compile and link.  ``defines`` are extra -D options (compile-time
+    configuration); ``lib`` is the output path (default: next to this file)."""
+    out = lib or LIB
+    objdir = os.path.join(os.path.dirname(out), "_build")
     os.makedirs(objdir, exist_ok=True)
     extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
+    extra += [f"-D{d}" for d in defines]
     objs = [os.path.join(objdir, s + ".o") for s in SOURCES]
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         logs = list(ex.map(lambda so: _compile(so[0], so[1], extra), zip(SOURCES, objs)))
     if resource_usage:
         with open(os.path.join(objdir, "resource_usage.log"), "w") as f:
             f.write("\n".join(logs))
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-8000:]}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {out}")
+    return out
 
 
 if __name__ == "__main__":
-    build(resource_usage="--resource-usage" in sys.argv, verbose=True)
+    defs = [a[2:] for a in sys.argv[1:] if a.startswith("-D")]
+    outs = [a.split("=", 1)[1] for a in sys.argv[1:] if a.startswith("--out=")]
+    build(resource_usage="--resource-usage" in sys.argv, verbose=True, defines=defs, lib=outs[0] if outs else None)

@@ -22,8 +22,18 @@ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 constexpr int ipowc(int b, int e) { return e == 0 ? 1 : b * ipowc(b, e - 1); }
 
 // ---------------------------------------------------------------- config
+// Compile-time configuration (values measured on MI355X; -D overrides them).
+#ifndef TFFT_E32
+#define TFFT_E32 8
+#endif
+#ifndef TFFT_E64
+#define TFFT_E64 8
+#endif
 // Elements held by one thread (the thread-level radix, Section IV-A.2).
-constexpr int cfg_E(int fp64, int M) { return M >= 8 ? 8 : M; }
+constexpr int cfg_E(int fp64, int M) {
+    const int e = fp64 ? TFFT_E64 : TFFT_E32;
+    return M >= e ? e : M;
+}
 // Signals held in LDS at once by one workgroup (the tile).  One-pass tiles
 // aim at 256 threads; multi-pass tiles are as wide as 512 threads and 64 KiB
 // of LDS allow (at most 32 signals), because the strided loads and the
@@ -41,8 +51,46 @@ constexpr int cfg_C(int fp64, int M, int kind) {
 // Keep the stage twiddles / the checksum vector of a thread in registers
 // across the signals it processes (1), or re-read them from the L1/L2
 // resident tables for every signal (0).
-constexpr int cfg_twreg(int fp64, int M, int kind) { return 0; }
-constexpr int cfg_creg(int fp64, int M, int kind) { return 0; }
+#ifndef TFFT_TWREG32
+#define TFFT_TWREG32 1
+#endif
+#ifndef TFFT_TWREG64
+#define TFFT_TWREG64 0
+#endif
+#ifndef TFFT_CREG32
+#define TFFT_CREG32 1
+#endif
+#ifndef TFFT_CREG64
+#define TFFT_CREG64 0
+#endif
+#ifndef TFFT_PREFETCH32
+#define TFFT_PREFETCH32 1
+#endif
+#ifndef TFFT_PREFETCH64
+#define TFFT_PREFETCH64 0
+#endif
+// Workgroups per launch: this many times the resident capacity of the chip
+// (0: at most 2048).
+#ifndef TFFT_GRID_MULT
+#define TFFT_GRID_MULT 0
+#endif
+// Streaming (non-temporal) global loads and stores of the signal data.
+#ifndef TFFT_NT
+#define TFFT_NT 1
+#endif
+// Total threads of one launch when it is not persistent (workgroups capped
+// at this divided by the workgroup size).
+#ifndef TFFT_GRID_THREADS
+#define TFFT_GRID_THREADS (4096 * 256)
+#endif
+// Largest log2(N) planned with two passes (three passes above).
+#ifndef TFFT_TWO_PASS_MAX_LOG2
+#define TFFT_TWO_PASS_MAX_LOG2 18
+#endif
+constexpr int cfg_twreg(int fp64, int M, int kind) { return fp64 ? TFFT_TWREG64 : TFFT_TWREG32; }
+constexpr int cfg_creg(int fp64, int M, int kind) { return fp64 ? TFFT_CREG64 : TFFT_CREG32; }
+// Issue the next tile's loads before transforming the current one.
+constexpr int cfg_prefetch(int fp64, int M, int kind) { return fp64 ? TFFT_PREFETCH64 : TFFT_PREFETCH32; }
 constexpr int cfg_threads(int fp64, int M, int kind) { return cfg_C(fp64, M, kind) * (M / cfg_E(fp64, M)); }
 
 // Radix sequence: as many stages of radix E as fit, then one stage of the
@@ -112,5 +160,7 @@ struct PassArgs {
 hipError_t launch_pass(int fp64, int M, int kind, int ft, const PassArgs &a, int grid, hipStream_t st);
 hipError_t launch_correct(int fp64, int M, int kind, const PassArgs &a, int grid, hipStream_t st);
 hipError_t launch_reset(DevReport *rep, hipStream_t st);
+// Resident workgroups of a pass kernel per compute unit (0 on error).
+int pass_occupancy(int fp64, int M, int kind, int ft);
 
 }  // namespace tfft

@@ -62,6 +62,30 @@ __device__ __forceinline__ void stg(cx<R> *p, cx<R> a) {
     v.y = a.im;
     *reinterpret_cast<typename vec2<R>::type *>(p) = v;
 }
+// Signal data: read once and written once per pass (streaming).
+template <typename R>
+using nvec2 = R __attribute__((ext_vector_type(2)));
+
+template <typename R>
+__device__ __forceinline__ cx<R> ld_stream(const cx<R> *p) {
+    if constexpr (TFFT_NT) {
+        const nvec2<R> v = __builtin_nontemporal_load(reinterpret_cast<const nvec2<R> *>(p));
+        return {v.x, v.y};
+    } else {
+        return ldg(p);
+    }
+}
+template <typename R>
+__device__ __forceinline__ void st_stream(cx<R> *p, cx<R> a) {
+    if constexpr (TFFT_NT) {
+        nvec2<R> v;
+        v.x = a.re;
+        v.y = a.im;
+        __builtin_nontemporal_store(v, reinterpret_cast<nvec2<R> *>(p));
+    } else {
+        stg(p, a);
+    }
+}
 
 template <int I, int N, typename F>
 __device__ __forceinline__ void static_for(F &&f) {
@@ -253,6 +277,42 @@ __device__ __forceinline__ double wave_sum(double v, int width) {
     return v;
 }
 
+// DPP moves of a 64-bit value (two 32-bit halves); lanes outside row_mask
+// read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+}
+
+// Sum over a full 64-lane wavefront with DPP lane moves (no LDS traffic):
+// butterflies inside quads and rows of 16, then the row broadcasts; the total
+// ends in lane 63.
+template <typename T, typename F>
+__device__ __forceinline__ T wave_sum_dpp(T v, F mv) {
+    v += mv.template operator()<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += mv.template operator()<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += mv.template operator()<0x124, 0xF>(v);  // row_ror:4
+    v += mv.template operator()<0x128, 0xF>(v);  // row_ror:8
+    v += mv.template operator()<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+    v += mv.template operator()<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+    return v;
+}
+struct Dpp64 {
+    template <int C, int RM>
+    __device__ __forceinline__ double operator()(double v) const { return dpp64<C, RM>(v); }
+};
+struct Dpp32 {
+    template <int C, int RM>
+    __device__ __forceinline__ float operator()(float v) const { return dpp32<C, RM>(v); }
+};
+
 // ------------------------------------------------------------- pass kernel
 template <typename R, int M, int KIND, bool FT>
 __global__ void __launch_bounds__(cfg_threads(sizeof(R) == 8, M, KIND))
@@ -322,23 +382,43 @@ pass_kernel(PassArgs a) {
     if (nwg % 8 == 0) wl = (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;  // XCD-contiguous group ranges
 
     const int rounds = a.G / C;
+    // Software pipeline: the loads of the next tile (next round, or round 0 of
+    // this workgroup's next group) are issued before the current tile is
+    // transformed, so every wavefront keeps two tiles of HBM reads in flight.
+    cx<R> nx[E];
+    auto load_tile = [&](int64_t gg, int rr) {
+        const MemberLoc Ln = member_loc<M, KIND, C>(a, gg, rr * C + c);
+        if (gg < a.n_groups && Ln.valid) {
+            const cx<R> *s = in + Ln.in_off;
+#pragma unroll
+            for (int m = 0; m < E; ++m) nx[m] = ld_stream(s + (uint32_t)(j + T * m) * Ln.in_stride);
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) nx[m] = cx<R>{R(0), R(0)};
+        }
+    };
+    constexpr bool PREFETCH = cfg_prefetch(FP64, M, KIND) != 0;
+    if constexpr (PREFETCH) load_tile(wl, 0);
     for (int64_t g = wl; g < a.n_groups; g += nwg) {
         const int fh = a.fault_head ? a.fault_head[g] : -1;
-        double D1r = 0.0, D1i = 0.0, D2r = 0.0, D2i = 0.0, Ssum = 0.0;
+        double D1r = 0.0, D1i = 0.0, D2r = 0.0, D2i = 0.0;
+        R Ssum = R(0);  // energy of the group's inputs, for the threshold only
         for (int r = 0; r < rounds; ++r) {
             const int b = r * C + c;
             const MemberLoc L = member_loc<M, KIND, C>(a, g, b);
             // offsets inside one signal are below N <= 2^24: 32-bit arithmetic
-            const cx<R> *src = in + L.in_off;
             cx<R> *dst = out + L.out_off;
-            const uint32_t istr = (uint32_t)L.in_stride, ostr = (uint32_t)L.out_stride;
+            const uint32_t ostr = (uint32_t)L.out_stride;
             cx<R> d[E];
-            if (L.valid) {
+            if constexpr (PREFETCH) {
 #pragma unroll
-                for (int m = 0; m < E; ++m) d[m] = ldg(src + (uint32_t)(j + T * m) * istr);
+                for (int m = 0; m < E; ++m) d[m] = nx[m];
+                if (r + 1 < rounds) load_tile(g, r + 1);
+                else load_tile(g + nwg, 0);
             } else {
+                load_tile(g, r);
 #pragma unroll
-                for (int m = 0; m < E; ++m) d[m] = cx<R>{R(0), R(0)};
+                for (int m = 0; m < E; ++m) d[m] = nx[m];
             }
             if constexpr (FT) {
                 double lr = 0.0, li = 0.0;
@@ -350,7 +430,7 @@ pass_kernel(PassArgs a) {
                     else cm = ldg(cv + j + T * m);
                     lr += cm.re * xr - cm.im * xi;
                     li += cm.re * xi + cm.im * xr;
-                    Ssum += xr * xr + xi * xi;
+                    Ssum += d[m].re * d[m].re + d[m].im * d[m].im;
                 }
                 const double w2 = double(b + 1);
                 D1r -= lr;
@@ -462,24 +542,37 @@ pass_kernel(PassArgs a) {
                 cx<R> *base = dst - c + c2;  // rows of one tile share the batch entry
                 if (L.valid) {
 #pragma unroll
-                    for (int m = 0; m < E; ++m) stg(base + (uint32_t)(j2 + T * m) * ostr, lds[lidx(c2, j2 + T * m)]);
+                    for (int m = 0; m < E; ++m) st_stream(base + (uint32_t)(j2 + T * m) * ostr, lds[lidx(c2, j2 + T * m)]);
                 }
                 __syncthreads();
             } else {
                 if (L.valid) {
 #pragma unroll
-                    for (int m = 0; m < E; ++m) stg(dst + (uint32_t)(j + T * m) * ostr, d[m]);
+                    for (int m = 0; m < E; ++m) st_stream(dst + (uint32_t)(j + T * m) * ostr, d[m]);
                 }
             }
         }  // rounds
 
         if constexpr (FT) {
-            double v[5] = {D1r, D1i, D2r, D2i, Ssum};
+            double v[5] = {D1r, D1i, D2r, D2i, 0.0};
+            if constexpr (NT % 64 == 0) {
 #pragma unroll
-            for (int k = 0; k < 5; ++k) v[k] = wave_sum(v[k], WIDTH);
-            if ((tid & 63) == 0) {
+                for (int q = 0; q < 4; ++q) v[q] = wave_sum_dpp(v[q], Dpp64{});
+                float sf = float(Ssum);
+                if constexpr (sizeof(R) == 8) v[4] = wave_sum_dpp(double(Ssum), Dpp64{});
+                else v[4] = double(wave_sum_dpp(sf, Dpp32{}));
+                if ((tid & 63) == 63) {
 #pragma unroll
-                for (int k = 0; k < 5; ++k) red[tid >> 6][k] = v[k];
+                    for (int q = 0; q < 5; ++q) red[tid >> 6][q] = v[q];
+                }
+            } else {
+                v[4] = double(Ssum);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) v[q] = wave_sum(v[q], WIDTH);
+                if ((tid & 63) == 0) {
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) red[tid >> 6][q] = v[q];
+                }
             }
             __syncthreads();
             if (tid == 0) {
@@ -766,6 +859,35 @@ hipError_t launch_pass(int fp64, int M, int kind, int ft, const PassArgs &a, int
 hipError_t launch_correct(int fp64, int M, int kind, const PassArgs &a, int grid, hipStream_t st) {
     if (fp64) return by_m<double>(M, [&](auto m) { return correct_m<double, decltype(m)::value>(kind, a, grid, st); });
     return by_m<float>(M, [&](auto m) { return correct_m<float, decltype(m)::value>(kind, a, grid, st); });
+}
+
+template <typename R, int M, int KIND, bool FT>
+static int occ_one() {
+    int n = 0;
+    constexpr int NT = cfg_threads(sizeof(R) == 8, M, KIND);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pass_kernel<R, M, KIND, FT>, NT, 0) != hipSuccess) return 0;
+    return n;
+}
+
+template <typename R, int M>
+static int occ_m(int kind, int ft) {
+    if (kind == KIND_ROWS) return ft ? occ_one<R, M, KIND_ROWS, true>() : occ_one<R, M, KIND_ROWS, false>();
+    if constexpr (M >= 16 && M <= 1024) {
+        if (kind == KIND_STRIDED) return ft ? occ_one<R, M, KIND_STRIDED, true>() : occ_one<R, M, KIND_STRIDED, false>();
+        if (kind == KIND_LAST) return ft ? occ_one<R, M, KIND_LAST, true>() : occ_one<R, M, KIND_LAST, false>();
+    }
+    return 0;
+}
+
+int pass_occupancy(int fp64, int M, int kind, int ft) {
+    int r = 0;
+    auto f = [&](auto m) {
+        r = fp64 ? occ_m<double, decltype(m)::value>(kind, ft) : occ_m<float, decltype(m)::value>(kind, ft);
+        return hipSuccess;
+    };
+    if (fp64) by_m<double>(M, f);
+    else by_m<float>(M, f);
+    return r;
 }
 
 hipError_t launch_reset(DevReport *rep, hipStream_t st) {

@@ -154,7 +154,7 @@ int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser) {
     P.E = cfg_E(fp64, M);
     P.C = cfg_C(fp64, M, kind);
     P.stages = n_stages(M, P.E);
-    const int G0 = Guser > 0 ? Guser : (kind == KIND_ROWS ? default_group(M) : 16);
+    const int G0 = Guser > 0 ? Guser : (kind == KIND_ROWS ? default_group(M) : 64);
     if (kind == KIND_ROWS) {
         if (G0 % P.C != 0) return TFFT_E_UNSUPPORTED;
         P.G = G0;
@@ -185,7 +185,15 @@ int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser) {
         P.n_strips = n_sub / P.C;
         P.n_groups = P.n_strips * ((P.n_outer + P.rb - 1) / P.rb);
     }
-    int64_t grid = std::min<int64_t>(P.n_groups, 2048);
+    int64_t cap = std::max<int64_t>(8, (int64_t)TFFT_GRID_THREADS / cfg_threads(fp64, M, kind));
+    if (TFFT_GRID_MULT > 0) {
+        // a persistent launch: TFFT_GRID_MULT x the workgroups resident at once
+        int cus = 0;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+        const int occ = std::max(1, pass_occupancy(fp64, M, kind, 1));
+        cap = std::max<int64_t>(8, (int64_t)TFFT_GRID_MULT * occ * std::max(1, cus));
+    }
+    int64_t grid = std::min<int64_t>(P.n_groups, cap);
     if (grid >= 8) grid = (grid + 7) / 8 * 8;
     P.grid = (int)std::max<int64_t>(1, grid);
     const double u = fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
@@ -382,13 +390,13 @@ int tfft_plan_create_with(tfft_plan *out, int64_t n, int64_t batch, int dtype, c
     p->kappa = (opt && opt->kappa > 0) ? opt->kappa : 16.0;
     const int k = ilog2_64(n);
     int rc = TFFT_OK;
-    // one pass up to 2^12; two passes of at most 2^8 each up to 2^16; three
+    // one pass up to 2^12; two passes up to 2^TFFT_TWO_PASS_MAX_LOG2; three
     // passes above, the shortest first (tiles of the strided passes then hold
     // >= 16 adjacent sub-signals, i.e. >= 128-byte segments per row)
     if (k <= 12) {
         p->passes = 1;
         p->lens[0] = (int)n;
-    } else if (k <= 16) {
+    } else if (k <= TFFT_TWO_PASS_MAX_LOG2) {
         p->passes = 2;
         p->lens[0] = 1 << (k / 2);
         p->lens[1] = 1 << (k - k / 2);
