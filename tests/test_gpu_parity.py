@@ -81,7 +81,7 @@ def test_multi_pass(tf, dtype, log2n, B, inverse):
     n = 1 << log2n
     x = inputs.uniform(3000 + log2n, B, n, NPDT[dtype])
     y, counts, recs, plan = run(tf, x, dtype, inverse=inverse)
-    assert plan.info()["passes"] == (2 if log2n <= 16 else 3)
+    assert plan.info()["passes"] == (2 if log2n <= 18 else 3)
     assert oracle.rel_l2(y, reference(x, inverse)) <= TOL[dtype]
     assert counts["detected"] == 0, recs
 
@@ -172,7 +172,7 @@ def test_every_stage_every_member(tf, dtype, log2n):
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("inverse", [False, True])
-@pytest.mark.parametrize("log2n,B", [(16, 4), (18, 3)])
+@pytest.mark.parametrize("log2n,B", [(16, 4), (20, 2)])
 def test_multi_pass_faults(tf, dtype, inverse, log2n, B):
     """A fault after every stage of every pass, and on the final values of
     every pass, in a random signal and element: detected in that pass and
@@ -212,7 +212,8 @@ def test_detect_mode_report_matches_oracle(tf):
     for g, o in zip(recs, orecs):
         assert g.member == o.located
         assert abs(g.residual - abs(o.d1)) <= 1e-6 * abs(o.d1)
-        assert abs(g.threshold - o.tau) <= 1e-9 * o.tau
+        # the energy S that scales tau is summed in the element precision
+        assert abs(g.threshold - o.tau) <= 1e-5 * o.tau
         assert abs(g.ratio - o.rho) <= 1e-6 * abs(o.rho)
     # outputs of DETECT mode are the faulty ones; the oracle corrects them
     fixed, _ = oracle.two_sided_batch(x, y, G, kappa=16.0, u=2.0 ** -24)
