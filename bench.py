@@ -48,9 +48,9 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="LOG2_BYTES",
                     help="only run a plain device-to-device copy of 2^LOG2_BYTES bytes (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
-    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_LOG2"),
-                    help="turn two rocprofv3 --pmc output directories (FETCH_SIZE, WRITE_SIZE) of a run that "
-                         "included the copy calibration into profiles/pmc_traffic.json and print a summary")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("READS_DIR", "WRITE_DIR", "COPY_LOG2"),
+                    help="turn rocprofv3 --pmc output directories (TCC_EA0_RDREQ_{32B,64B,128B}_sum, WRITE_SIZE) "
+                         "of runs that included the copy calibration into profiles/pmc_traffic.json")
     ap.add_argument("--ft", default="correct", choices=["off", "detect", "correct"],
                     help="fault-tolerance mode of the timed workload (the headline uses correct)")
     return ap.parse_args()
@@ -111,44 +111,48 @@ def copy_calibration(log2_bytes):
     print(json.dumps({"copy_bytes": n, "launches": 3}), flush=True)
 
 
-def summarize_pmc(fetch_dir, write_dir, copy_log2, label_dt, label_k):
-    """Per-launch HBM traffic of each pass kernel from two rocprofv3 --pmc runs
-    (FETCH_SIZE, WRITE_SIZE: KiB per dispatch), each scaled by what the same
-    counter reads for a plain copy of known size."""
+def summarize_pmc(reads_dir, write_dir, copy_log2, label_dt, label_k):
+    """Per-launch HBM traffic of each pass kernel from rocprofv3 --pmc runs.
+
+    Reads: the TCC_EA0_RDREQ_{32B,64B,128B} request counts (on gfx950 the
+    derived FETCH_SIZE counts 128-byte requests as 64 bytes).  Writes:
+    WRITE_SIZE (KiB).  Each is scaled by what the same counters read for a
+    plain copy of 2^copy_log2 bytes recorded in the same runs."""
     import csv
     import glob
 
-    def read(d, counter):
+    def read(d):
         rows = {}
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for r in csv.DictReader(open(f)):
-                if r["Counter_Name"] != counter:
-                    continue
-                rows.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        return rows
-    copy_bytes = 1 << int(copy_log2)
-    fetch, write = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
+                rows.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        return {k: {c: sorted(v)[len(v) // 2] for c, v in cs.items()} for k, cs in rows.items()}
 
-    def copy_kib(rows):
-        cands = [v for k, v in rows.items() if "copy" in k.lower() or "elementwise" in k.lower()]
-        vals = [x for v in cands for x in v if x * 1024 > 0.5 * copy_bytes]
-        return sorted(vals)[len(vals) // 2] if vals else None
-    cf, cw = copy_kib(fetch), copy_kib(write)
-    sf = copy_bytes / (cf * 1024) if cf else None
-    sw = copy_bytes / (cw * 1024) if cw else None
+    def read_bytes(c):
+        return (32 * c.get("TCC_EA0_RDREQ_32B_sum", 0) + 64 * c.get("TCC_EA0_RDREQ_64B_sum", 0)
+                + 128 * c.get("TCC_EA0_RDREQ_128B_sum", 0))
+    copy_bytes = 1 << int(copy_log2)
+    reads, writes = read(reads_dir), read(write_dir)
+    iscopy = lambda k: "copybuffer" in k.lower()
+    cr = [read_bytes(c) for k, c in reads.items() if iscopy(k) and read_bytes(c) > 0.5 * copy_bytes]
+    cw = [c["WRITE_SIZE"] * 1024 for k, c in writes.items() if iscopy(k) and "WRITE_SIZE" in c
+          and c["WRITE_SIZE"] * 1024 > 0.5 * copy_bytes]
+    sr = copy_bytes / cr[0] if cr else None
+    sw = copy_bytes / cw[0] if cw else None
     src = os.path.join(ROOT, "paper_2405_02520_amd", "csrc", "tfft_kernels.hip")
     out = {"kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
-           "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
-           "fetch_scale": sf, "write_scale": sw, "entries": {}}
-    lines = [f"copy of {copy_bytes} B: FETCH_SIZE {cf} KiB, WRITE_SIZE {cw} KiB -> scale {sf}, {sw}"]
+           "copy_bytes": copy_bytes, "copy_read_bytes": cr[0] if cr else None,
+           "copy_write_bytes": cw[0] if cw else None, "read_scale": sr, "write_scale": sw, "entries": {}}
+    lines = [f"copy of {copy_bytes} B: reads {out['copy_read_bytes']} B, writes {out['copy_write_bytes']} B "
+             f"-> scales {sr}, {sw}"]
     label = f"{label_dt}_k{label_k}"
-    for name in sorted(set(fetch) & set(write)):
-        if "pass_kernel" not in name:
+    for name in sorted(set(reads) & set(writes)):
+        if "pass_kernel" not in name or "WRITE_SIZE" not in writes[name]:
             continue
-        f = sorted(fetch[name])[len(fetch[name]) // 2] * 1024 * (sf or 1.0)
-        w = sorted(write[name])[len(write[name]) // 2] * 1024 * (sw or 1.0)
-        out["entries"][f"{label} {name}"] = {"fetch_bytes": f, "write_bytes": w, "traffic_bytes": f + w}
-        lines.append(f"{label} {name}: fetch {f / 2**30:.3f} GiB, write {w / 2**30:.3f} GiB per launch")
+        f = read_bytes(reads[name]) * (sr or 1.0)
+        w = writes[name]["WRITE_SIZE"] * 1024 * (sw or 1.0)
+        out["entries"][f"{label} {name}"] = {"read_bytes": f, "write_bytes": w, "traffic_bytes": f + w}
+        lines.append(f"{label} {name}: read {f / 2**30:.3f} GiB, write {w / 2**30:.3f} GiB per launch")
     with open(os.path.join(ROOT, "profiles", "pmc_traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     print("\n".join(lines))

@@ -709,63 +709,100 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
             }
         }
 
-        // transform of the combined input, fp64, Stockham radix-2 in LDS
-        for (int n = tid; n < M; n += kCorrThreads) {
+        // Member sums are taken with lanes along the C adjacent members of a
+        // tile when those are adjacent in memory (strided passes; outputs of
+        // the last pass), else along the positions; the C lanes that share a
+        // position are then summed with lane shuffles.
+        constexpr int CL = (KIND == KIND_ROWS) ? 1 : C;
+        constexpr bool IN_ALONG_MEMBERS = KIND == KIND_STRIDED;
+        constexpr bool OUT_ALONG_MEMBERS = KIND != KIND_ROWS;
+        auto member_sum = [&](bool along_members, int n, auto &&value) -> cx<double> {
+            // sum over the members of `value(L, n)`; the calling lanes share n
+            // in groups of CL adjacent lanes when along_members
             cx<double> acc{0.0, 0.0};
-            for (int b = 0; b < a.G; ++b) {
-                const MemberLoc L = member_loc<M, KIND, C>(a, g, b);
-                if (L.valid) acc = cadd(acc, load_in(L, n));
+            if (along_members) {
+                const int c = tid % CL;
+                for (int ru = 0; ru * CL < a.G; ++ru) {
+                    const int bm = ru * CL + c;
+                    const MemberLoc L = member_loc<M, KIND, C>(a, g, bm);
+                    if (L.valid) acc = cadd(acc, value(L, bm, n));
+                }
+                for (int off = 1; off < CL; off *= 2) {
+                    acc.re += __shfl_xor(acc.re, off, 64);
+                    acc.im += __shfl_xor(acc.im, off, 64);
+                }
+            } else {
+                for (int bm = 0; bm < a.G; ++bm) {
+                    const MemberLoc L = member_loc<M, KIND, C>(a, g, bm);
+                    if (L.valid) acc = cadd(acc, value(L, bm, n));
+                }
             }
-            if (a.conj_in) acc.im = -acc.im;
-            buf[0][n] = acc;
+            return acc;
+        };
+
+        // transform of the combined input, fp64, Stockham radix-2 in LDS
+        {
+            const int step = IN_ALONG_MEMBERS ? kCorrThreads / CL : kCorrThreads;
+            const int n0 = IN_ALONG_MEMBERS ? tid / CL : tid;
+            for (int n = n0; n < M; n += step) {
+                cx<double> acc = member_sum(IN_ALONG_MEMBERS, n, [&](const MemberLoc &L, int, int nn) {
+                    return load_in(L, nn);
+                });
+                if (a.conj_in) acc.im = -acc.im;
+                if (!IN_ALONG_MEMBERS || tid % CL == 0) buf[0][n] = acc;
+            }
         }
         __syncthreads();
         int src = 0;
         for (int ns = 1; ns < M; ns *= 2) {
             for (int t = tid; t < M / 2; t += kCorrThreads) {
-                const int k = t & (ns - 1);
-                const cx<double> w = w64[k * (M / (2 * ns))];
+                const int kk = t & (ns - 1);
+                const cx<double> w = w64[kk * (M / (2 * ns))];
                 const cx<double> x0 = buf[src][t];
                 const cx<double> x1 = cmul(buf[src][t + M / 2], w);
-                const int o = (t / ns) * 2 * ns + k;
+                const int o = (t / ns) * 2 * ns + kk;
                 buf[src ^ 1][o] = cadd(x0, x1);
                 buf[src ^ 1][o + ns] = csub(x0, x1);
             }
             __syncthreads();
             src ^= 1;
         }
-        for (int k = tid; k < M; k += kCorrThreads) {
-            cx<double> p = buf[src][k];
+        for (int kk = tid; kk < M; kk += kCorrThreads) {
+            cx<double> p = buf[src][kk];
             if (a.conj_out) p.im = -p.im;
             p.re *= a.out_scale;
             p.im *= a.out_scale;
-            buf[src][k] = p;
+            buf[src][kk] = p;
+        }
+        __syncthreads();
+
+        // P - sum of the (un-twiddled) outputs of the members other than jl
+        // (jl < 0: of all members) -> LDS buf[src ^ 1]
+        {
+            const int step = OUT_ALONG_MEMBERS ? kCorrThreads / CL : kCorrThreads;
+            const int k0 = OUT_ALONG_MEMBERS ? tid / CL : tid;
+            for (int kk = k0; kk < M; kk += step) {
+                const cx<double> s = member_sum(OUT_ALONG_MEMBERS, kk, [&](const MemberLoc &L, int bm, int k2) {
+                    return bm == jl ? cx<double>{0.0, 0.0} : cmulconj(load_out(L, k2), applied(L, k2));
+                });
+                if (!OUT_ALONG_MEMBERS || tid % CL == 0) buf[src ^ 1][kk] = csub(buf[src][kk], s);
+            }
         }
         __syncthreads();
 
         int action;
         if (jl >= 0) {
             const MemberLoc Lj = member_loc<M, KIND, C>(a, g, jl);
-            for (int k = tid; k < M; k += kCorrThreads) {
-                cx<double> acc = buf[src][k];
-                for (int b = 0; b < a.G; ++b) {
-                    if (b == jl) continue;
-                    const MemberLoc L = member_loc<M, KIND, C>(a, g, b);
-                    if (L.valid) acc = csub(acc, cmulconj(load_out(L, k), applied(L, k)));
-                }
-                const cx<double> y = cmul(acc, applied(Lj, k));
-                stg(out + Lj.out_off + (uint32_t)k * Lj.out_stride, cx<R>{R(y.re), R(y.im)});
+            for (int kk = tid; kk < M; kk += kCorrThreads) {
+                const cx<double> y = cmul(buf[src ^ 1][kk], applied(Lj, kk));
+                stg(out + Lj.out_off + (uint32_t)kk * Lj.out_stride, cx<R>{R(y.re), R(y.im)});
             }
             action = 2;
         } else {
             double nrm = 0.0;
-            for (int k = tid; k < M; k += kCorrThreads) {
-                cx<double> acc = buf[src][k];
-                for (int b = 0; b < a.G; ++b) {
-                    const MemberLoc L = member_loc<M, KIND, C>(a, g, b);
-                    if (L.valid) acc = csub(acc, cmulconj(load_out(L, k), applied(L, k)));
-                }
-                nrm += acc.re * acc.re + acc.im * acc.im;
+            for (int kk = tid; kk < M; kk += kCorrThreads) {
+                const cx<double> v = buf[src ^ 1][kk];
+                nrm += v.re * v.re + v.im * v.im;
             }
             nrm = block_sum(nrm, scratch);
             action = (sqrt(nrm) <= rec.tau) ? 3 : 4;

@@ -336,7 +336,10 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
         if (launch_pass(fp64, P.M, P.kind, ft, A, P.grid, st) != hipSuccess) return TFFT_E_HIP;
         if (timed && hipEventRecord(p->ev[1 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
         if (mode == TFFT_FT_CORRECT) {
-            if (launch_correct(fp64, P.M, P.kind, A, 64, st) != hipSuccess) return TFFT_E_HIP;
+            // one workgroup per possible record, at most 1024; a workgroup
+            // with no record of this pass exits at once
+            const int cgrid = (int)std::min<int64_t>(1024, std::max<int64_t>(1, P.n_groups));
+            if (launch_correct(fp64, P.M, P.kind, A, cgrid, st) != hipSuccess) return TFFT_E_HIP;
         }
         if (timed && hipEventRecord(p->ev[2 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
     }
