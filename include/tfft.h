@@ -125,8 +125,12 @@ typedef struct {
     double ratio_re, ratio_im; /* d2 / d1 */
 } tfft_record;
 
-/* Test instrument: one additive fault.  `value` (dre + i dim) is added to a
- * register of the transform of signal `signal` in pass `pass`:
+/* Kinds of injected faults: an additive value (the paper's register offset)
+ * or one flipped bit (the paper's bit-flip protocol, Section II-A). */
+enum tfft_fault_mode { TFFT_FAULT_ADD = 0, TFFT_FAULT_FLIP_RE = 1, TFFT_FAULT_FLIP_IM = 2 };
+
+/* Test instrument: one fault in a register of the transform of signal
+ * `signal` in pass `pass` (an additive value or one flipped bit):
  *   stage >= 0: to output `index` of butterfly stage `stage` (position in that
  *               stage's output array, after the stage's butterflies);
  *   stage == -1: to final output value `index` of the pass (after the
@@ -143,7 +147,11 @@ typedef struct {
     int32_t pass;
     int32_t stage;
     int64_t index;
-    double dre, dim;
+    double dre, dim;  /* TFFT_FAULT_ADD: value added */
+    int32_t mode;     /* enum tfft_fault_mode */
+    int32_t bit;      /* TFFT_FAULT_FLIP_*: bit of the IEEE representation of the
+                         real or imaginary part (0 = least significant; < 32 for
+                         complex64, < 64 for complex128) */
 } tfft_fault;
 
 /* Create a plan for `batch` transforms of length `n` (a power of two,

@@ -69,7 +69,11 @@ class tfft_record(ctypes.Structure):
 
 class tfft_fault(ctypes.Structure):
     _fields_ = [("signal", ctypes.c_int64), ("pass_", ctypes.c_int32), ("stage", ctypes.c_int32),
-                ("index", ctypes.c_int64), ("dre", ctypes.c_double), ("dim", ctypes.c_double)]
+                ("index", ctypes.c_int64), ("dre", ctypes.c_double), ("dim", ctypes.c_double),
+                ("mode", ctypes.c_int32), ("bit", ctypes.c_int32)]
+
+
+FAULT_ADD, FAULT_FLIP_RE, FAULT_FLIP_IM = 0, 1, 2
 
 
 _P = ctypes.c_void_p
@@ -203,13 +207,15 @@ class Plan:
         return self._exec(tfft_exec_inverse, x, out, ft_mode, stream)
 
     def set_faults(self, faults):
-        """faults: iterable of dicts with keys signal, pass_, stage, index, value (complex)."""
+        """faults: iterable of dicts with keys signal, pass_, stage, index and
+        either value (complex, added) or flip ("re" | "im") with bit."""
         faults = list(faults)
         arr = (tfft_fault * max(1, len(faults)))()
         for i, f in enumerate(faults):
             v = complex(f.get("value", 0.0))
+            mode = {None: FAULT_ADD, "re": FAULT_FLIP_RE, "im": FAULT_FLIP_IM}[f.get("flip")]
             arr[i] = tfft_fault(int(f["signal"]), int(f.get("pass_", 0)), int(f.get("stage", -1)),
-                                int(f["index"]), v.real, v.imag)
+                                int(f["index"]), v.real, v.imag, mode, int(f.get("bit", 0)))
         _check(tfft_set_faults(self._h, arr, len(faults)), "tfft_set_faults")
 
     def set_timing(self, enable: bool = True):

@@ -34,6 +34,15 @@ constexpr int cfg_E(int fp64, int M) {
     const int e = fp64 ? TFFT_E64 : TFFT_E32;
     return M >= e ? e : M;
 }
+// Threads of a multi-pass tile (a 512-thread workgroup caps a wavefront at
+// 256 VGPRs, a 256-thread one lets the compiler use the accumulation
+// registers as well).
+#ifndef TFFT_MP_THREADS32
+#define TFFT_MP_THREADS32 512
+#endif
+#ifndef TFFT_MP_THREADS64
+#define TFFT_MP_THREADS64 512
+#endif
 // Signals held in LDS at once by one workgroup (the tile).  One-pass tiles
 // aim at 256 threads; multi-pass tiles are as wide as 512 threads and 64 KiB
 // of LDS allow (at most 32 signals), because the strided loads and the
@@ -44,7 +53,7 @@ constexpr int cfg_C(int fp64, int M, int kind) {
     const int S = fp64 ? 16 : 8;
     int c = kind == KIND_ROWS ? 256 / (T > 0 ? T : 1) : 32;
     if (kind == KIND_ROWS && c > 16) c = 16;
-    const int maxthr = kind == KIND_ROWS ? 256 : 512;
+    const int maxthr = kind == KIND_ROWS ? 256 : (fp64 ? TFFT_MP_THREADS64 : TFFT_MP_THREADS32);
     while (c > 1 && (c * T > maxthr || c * M * S > 65536)) c /= 2;
     return c < 1 ? 1 : c;
 }
@@ -119,8 +128,10 @@ struct DevFault {
     int32_t stage;   // butterfly stage, -1 = final value
     int32_t j, m;    // thread within the signal, register index
     int32_t next;    // next fault of the same group, -1 = end
-    int32_t pad_;
+    int32_t mode;    // 0 add, 1 flip a bit of re, 2 flip a bit of im
     double dre, dim;
+    int32_t bit;
+    int32_t pad_;
 };
 
 // Geometry and tables of one pass launch.

@@ -237,35 +237,51 @@ __device__ __forceinline__ cx<double> itw(const PassArgs &a, int64_t t) {
 // register array of the caller is never address-taken (it would be placed in
 // scratch memory).
 struct FaultHit {
-    int m;
-    double dre, dim;
+    int m;                  // register index, -1 = none
+    double dre, dim;        // additive part
+    unsigned long long fre, fim;  // bit masks to flip in re / im
 };
 
 __device__ __forceinline__ FaultHit find_fault(const DevFault *F, int fh, int stage, int b, int j) {
-    FaultHit h{-1, 0.0, 0.0};
+    FaultHit h{-1, 0.0, 0.0, 0ull, 0ull};
     for (int f = fh; f >= 0; f = F[f].next) {
         const DevFault x = F[f];
         if (x.stage == stage && x.member == b && x.j == j) {
             if (h.m < 0 || h.m == x.m) {
                 h.m = x.m;
-                h.dre += x.dre;
-                h.dim += x.dim;
+                if (x.mode == 0) {
+                    h.dre += x.dre;
+                    h.dim += x.dim;
+                } else if (x.mode == 1) {
+                    h.fre ^= 1ull << x.bit;
+                } else {
+                    h.fim ^= 1ull << x.bit;
+                }
             }
         }
     }
     return h;
 }
 
+__device__ __forceinline__ float flip_bits(float v, unsigned long long mask) {
+    return __uint_as_float(__float_as_uint(v) ^ (unsigned int)mask);
+}
+__device__ __forceinline__ double flip_bits(double v, unsigned long long mask) {
+    return __longlong_as_double(__double_as_longlong(v) ^ (long long)mask);
+}
+
 template <typename R, int E>
 __device__ __forceinline__ void apply_faults(cx<R> (&d)[E], const DevFault *F, int fh, int stage, int b, int j) {
     const FaultHit h = find_fault(F, fh, stage, b, j);
-    // every register takes an addend that is zero except at h.m: written as
-    // an add of a selected value (not a conditional update) so the compiler
-    // cannot turn it into an indexed store that would demote d[] to scratch
+    // Every register takes an addend and a flip mask that are zero except at
+    // h.m: written as an add of a selected value and an xor with a selected
+    // mask (not a conditional update) so the compiler cannot turn it into an
+    // indexed store that would demote d[] to scratch memory.
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        d[m].re += (m == h.m) ? R(h.dre) : R(0);
-        d[m].im += (m == h.m) ? R(h.dim) : R(0);
+        const bool hit = m == h.m;
+        d[m].re = flip_bits(d[m].re + (hit ? R(h.dre) : R(0)), hit ? h.fre : 0ull);
+        d[m].im = flip_bits(d[m].im + (hit ? R(h.dim) : R(0)), hit ? h.fim : 0ull);
     }
 }
 

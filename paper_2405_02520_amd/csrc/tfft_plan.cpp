@@ -549,6 +549,9 @@ int tfft_set_faults(tfft_plan p, const tfft_fault *specs, int64_t n) {
         const tfft_fault &s = specs[f];
         if (s.signal < 0 || s.signal >= p->batch || s.pass < 0 || s.pass >= p->passes) return TFFT_E_INVALID;
         if (s.index < 0 || s.index >= p->n) return TFFT_E_INVALID;
+        if (s.mode < TFFT_FAULT_ADD || s.mode > TFFT_FAULT_FLIP_IM) return TFFT_E_INVALID;
+        if (s.mode != TFFT_FAULT_ADD && (s.bit < 0 || s.bit >= (p->dtype == TFFT_C128 ? 64 : 32)))
+            return TFFT_E_INVALID;
         const PassPlan &P = p->pass[s.pass];
         if (s.stage < -1 || s.stage >= P.stages) return TFFT_E_INVALID;
         const int M = P.M, E = P.E, T = M / E;
@@ -577,8 +580,10 @@ int tfft_set_faults(tfft_plan p, const tfft_fault *specs, int64_t n) {
         d.group = g;
         d.member = b;
         d.stage = s.stage;
-        d.dre = s.dre;
-        d.dim = s.dim;
+        d.dre = s.mode == TFFT_FAULT_ADD ? s.dre : 0.0;
+        d.dim = s.mode == TFFT_FAULT_ADD ? s.dim : 0.0;
+        d.mode = s.mode;
+        d.bit = s.bit;
         if (s.stage < 0) {
             d.j = (int)(pos % T);
             d.m = (int)(pos / T);

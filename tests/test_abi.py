@@ -80,5 +80,5 @@ def test_null_plan_is_rejected(tf):
 
 def test_record_layouts_match_header(tf):
     assert ctypes.sizeof(tf.tfft_record) == 8 * 3 + 4 * 4 + 8 * 4
-    assert ctypes.sizeof(tf.tfft_fault) == 8 + 4 + 4 + 8 + 16
+    assert ctypes.sizeof(tf.tfft_fault) == 8 + 4 + 4 + 8 + 16 + 8
     assert ctypes.sizeof(tf.tfft_counts) == 7 * 8

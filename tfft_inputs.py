@@ -72,3 +72,9 @@ def dynamic(seed: int, batch: int, n: int, dtype=np.complex64) -> np.ndarray:
     mag = np.exp(sigma * rng.standard_normal(size=(batch, n)))
     phase = rng.uniform(0.0, 2.0 * math.pi, size=(batch, n))
     return _as_complex(mag * np.cos(phase), mag * np.sin(phase), dtype)
+
+
+def real_gaussian(seed: int, shape) -> np.ndarray:
+    """Real N(0, 1) weights (float64), e.g. the fixed weights of the
+    differentiable-layer loss sum |W * FFT(x)|^2."""
+    return np.random.default_rng(seed).standard_normal(size=shape)
