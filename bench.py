@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("READS_DIR", "WRITE_DIR", "COPY_LOG2"),
                     help="turn rocprofv3 --pmc output directories (TCC_EA0_RDREQ_{32B,64B,128B}_sum, WRITE_SIZE) "
                          "of runs that included the copy calibration into profiles/pmc_traffic.json")
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "grad", "bitflip", "ragged"],
+                    help="sweep: the throughput sweep (default, the headline line); grad: the differentiable "
+                         "layer, complex64 [2048, 4096] forward + backward; bitflip: the fault-coverage campaign; "
+                         "ragged: 4096 complex64 signals of lengths 2^U{6..20} in one graph launch")
     ap.add_argument("--ft", default="correct", choices=["off", "detect", "correct"],
                     help="fault-tolerance mode of the timed workload (the headline uses correct)")
     return ap.parse_args()
@@ -158,8 +162,153 @@ def summarize_pmc(reads_dir, write_dir, copy_log2, label_dt, label_k):
     print("\n".join(lines))
 
 
+def bench_grad(args):
+    """Differentiable layer: x complex64 [2048, 4096], loss sum |W * FFT(x)|^2
+    with W ~ N(0,1); one step = forward transform + backward (adjoint)
+    transform, both with the two-sided checksum; the loss arithmetic between
+    them is torch elementwise work inside the step."""
+    import numpy as np
+    import torch
+
+    from paper_2405_02520_amd import layer
+    import tfft_inputs as inputs
+
+    B, n = 2048, 4096
+    x = torch.from_numpy(inputs.uniform(inputs.SEED_GRAD, B, n, np.complex64)).cuda().requires_grad_(True)
+    w2 = torch.from_numpy((inputs.real_gaussian(inputs.SEED_GRAD + 1, (B, n)) ** 2).astype(np.float32)).cuda()
+
+    def step(mode):
+        x.grad = None
+        y = layer.fft(x, ft_mode=mode)
+        (w2 * (y.real ** 2 + y.imag ** 2)).sum().backward()
+
+    res = {}
+    for mode in ("off", "correct"):
+        for _ in range(max(1, args.warmup)):
+            step(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(mode)
+        torch.cuda.synchronize()
+        res[mode] = (time.perf_counter() - t0) * 1e3 / args.steps
+    fl = 2 * 5.0 * n * math.log2(n) * B
+    out = {"metric": "GFLOP/s of the differentiable FT-FFT layer (forward + backward transforms)",
+           "value": round(fl / (res["correct"] * 1e-3) / 1e9, 1), "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["correct"], 4),
+           "ms_per_step_ft_off": round(res["off"], 4), "ft_overhead_pct": round((res["correct"] / res["off"] - 1) * 100, 2),
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic: U[-1,1) complex, W ~ N(0,1)",
+           "config": {"workload": "differentiable layer, complex64 [2048, 4096], loss sum |W*FFT(x)|^2, forward + backward"}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_bitflip(args):
+    """The paper's fault-coverage protocol: 2000 test sequences (checksum
+    groups of 16 signals of length 1024), one random bit flipped in half of
+    them; ROC of the threshold and the CORRECT-mode outcome."""
+    import numpy as np
+    import torch
+
+    from paper_2405_02520_amd import campaign
+    import tfft_inputs as inputs
+
+    n, G, groups = 1024, 16, 2000
+    out = {"metric": "bit-flip fault coverage of the two-sided checksum", "config": {
+        "workload": f"{groups} groups of {G} N(0,1) signals of length {n}, one random single-bit flip in half of "
+                    "the groups (random stage or final value, element, re/im part, bit)"}, "results": {}}
+    for dt in args.dtypes.split(","):
+        x = inputs.gaussian(inputs.SEED_PRECISION + (100 if dt == "c128" else 0), groups * G, n,
+                            np.complex64 if dt == "c64" else np.complex128)
+        res = campaign.run(torch.from_numpy(x).cuda(), G, seed=(inputs.SEED_PRECISION + 7) ^ 0xFA17)
+        bits = np.array([f["bit"] for f in res["specs"]])
+        faulty = res["faulty"]
+        r = res["ratio"][faulty]
+        width = 32 if dt == "c64" else 64
+        mant = 23 if dt == "c64" else 52
+        classes = {"mantissa_low": bits < mant // 2, "mantissa_high": (bits >= mant // 2) & (bits < mant),
+                   "exponent": (bits >= mant) & (bits < width - 1), "sign": bits == width - 1}
+        det16 = ~(r <= 16.0)
+        out["results"][dt] = {
+            "roc_kappa_detection_falsealarm": [[round(k, 3), d, f] for k, d, f in res["roc"][::5]],
+            "at_kappa_16": {"detected_faulty": res["detected_faulty"], "faulty": int(len(faulty)),
+                            "false_alarms": res["false_alarms"], "clean": int(groups - len(faulty)),
+                            "corrected": res["counts"]["corrected"], "uncorrectable": res["counts"]["uncorrectable"]},
+            "detection_rate_by_bit_class": {k: (round(float(det16[m].mean()), 4) if m.any() else None)
+                                            for k, m in classes.items()},
+            "max_clean_ratio": float(np.max(res["ratio"][np.setdiff1d(np.arange(groups), faulty)])),
+        }
+    print(json.dumps(out), flush=True)
+
+
+def bench_ragged(args):
+    """Ragged batch: 4096 complex64 signals of lengths 2^k, k ~ U{6..20},
+    packed back to back, inputs U[-1, 1); per-length plans chosen by the
+    autotuner; faults injected into 1% of the signals; one step = one replay
+    of the captured graph with fault tolerance CORRECT.  Also timed: the same
+    with FT off, and eager launches (no graph)."""
+    import numpy as np
+    import torch
+
+    import paper_2405_02520_amd as tf
+    import tfft_inputs as inputs
+
+    count = 4096
+    lengths = inputs.ragged_lengths(inputs.SEED_RAGGED, count, 6, 20)
+    total = int(lengths.sum())
+    xd = torch.from_numpy(inputs.uniform_flat(inputs.SEED_RAGGED, total, np.complex64)).cuda()
+    out = torch.empty_like(xd)
+    rg = tf.Ragged(lengths, dtype="c64")
+    st = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(st):
+        rg.tune(xd, out, reps=2)
+    st.synchronize()
+    tune_s = time.perf_counter() - t0
+    rng = inputs.fault_rng(inputs.SEED_RAGGED)
+    sigs = inputs.ragged_fault_signals(rng, lengths, count // 100)  # at most one per checksum group
+    rg.set_faults([dict(signal=int(s), stage=-1, index=int(rng.integers(lengths[s])),
+                        value=complex(rng.uniform(0.5, 4.0), rng.uniform(-4.0, 4.0))) for s in sigs])
+
+    def timed(mode, graph):
+        with torch.cuda.stream(st):
+            for _ in range(max(1, args.warmup)):
+                rg.forward(xd, out, ft_mode=mode, use_graph=graph)
+            st.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                rg.forward(xd, out, ft_mode=mode, use_graph=graph)
+            st.synchronize()
+        return (time.perf_counter() - t) * 1e3 / args.steps
+
+    ms_off = timed("off", True)
+    ms_eager = timed("correct", False)
+    ms = timed("correct", True)
+    counts, _ = rg.report()
+    fl = float(np.sum(5.0 * lengths * np.log2(lengths)))
+    gbs = 2 * 8 * total / (ms * 1e-3) / 1e9
+    classes = [{"n": n, "signals": c, "passes": d["passes"], "pass_len": d["pass_len"], "group": d["group"]}
+               for n, c, d in rg.info()]
+    res = {"metric": "GFLOP/s & HBM GB/s, ragged batched C2C FFT with checksum (one graph launch)",
+           "value": round(fl / (ms * 1e-3) / 1e9, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic: U[-1,1) complex", "effective_GBps": round(gbs, 1),
+           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "ms_ft_off_graph": round(ms_off, 4),
+           "ms_ft_correct_eager": round(ms_eager, 4), "ft_overhead_pct": round((ms / ms_off - 1) * 100, 2),
+           "faults_injected": int(len(sigs)), "corrected": counts["corrected"],
+           "uncorrectable": counts["uncorrectable"], "tune_s": round(tune_s, 2), "classes": classes,
+           "config": {"workload": f"ragged: {count} complex64 signals, lengths 2^k with k ~ U{{6..20}} "
+                                  f"({total} elements), faults in 1% of signals, autotuned, one graph replay"}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "ragged":
+        return bench_ragged(args)
+    if args.workload == "grad":
+        return bench_grad(args)
+    if args.workload == "bitflip":
+        return bench_bitflip(args)
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, args.dtypes, args.kmin)
         return
@@ -168,7 +317,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; a batched FFT shards on the batch axis with no "
-              "exchange (see DESIGN.md).  Run with --gpus 1.", file=sys.stderr)
+              "exchange.  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

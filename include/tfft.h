@@ -81,7 +81,12 @@ typedef struct {
     uint32_t flags;  /* enum tfft_flags */
     int32_t group;   /* signals per checksum group G (a power of two, 1..64); 0 = default */
     double kappa;    /* threshold factor; 0 = default (16) */
-    int32_t reserved[8];
+    int32_t passes;  /* 0 = automatic; 1, 2 or 3 forces the number of passes (n <= 2^12
+                        for 1, 2^8 <= n <= 2^20 for 2, n >= 2^12 for 3); another
+                        length gives E_UNSUPPORTED */
+    int32_t grid_scale; /* 0 = default; else workgroups per launch = default * 2^grid_scale
+                           (-3..3), a tuning knob */
+    int32_t reserved[6];
 } tfft_options;
 
 /* Description of a plan (tfft_plan_info). */
@@ -203,6 +208,45 @@ int tfft_plan_info(tfft_plan p, tfft_plan_desc *info);
  * E_STATE if timing was off for the last execution. */
 int tfft_set_timing(tfft_plan p, int enable);
 int tfft_get_timings(tfft_plan p, double *pass_ms, double *correct_ms);
+
+/* ------------------------------------------------------------------------
+ * Ragged batches: `count` signals of power-of-two lengths lengths[i]
+ * (2..2^24) stored at element offsets offsets[i] of the input and output
+ * buffers, signal i occupying [offsets[i], offsets[i] + lengths[i]) of each
+ * (signals must not overlap each other).  Signals of one length form a class
+ * that is transformed by one plan addressing the signals through a device
+ * offset table (no repacking).  Records and faults use the index i.
+ * ------------------------------------------------------------------------ */
+typedef struct tfft_ragged_s *tfft_ragged;
+
+int tfft_ragged_create(tfft_ragged *out, int64_t count, const int64_t *lengths, const int64_t *offsets, int dtype,
+                       const tfft_options *opt);
+int tfft_ragged_destroy(tfft_ragged r);
+
+/* Transform every signal (forward, or inverse when inverse != 0).  With
+ * use_graph != 0 all launches of all classes are captured once into a HIP
+ * graph (per buffers, mode and direction) and replayed as one graph launch;
+ * hip_stream must then be a non-null stream.  Asynchronous. */
+int tfft_ragged_exec(tfft_ragged r, const void *d_in, void *d_out, int ft_mode, int inverse, int use_graph,
+                     void *hip_stream);
+
+/* Merged report of the last execution (records carry the ragged index i). */
+int tfft_ragged_get_report(tfft_ragged r, tfft_counts *counts, tfft_record *recs, int64_t cap);
+
+/* Test hook; specs[k].signal is the ragged index. */
+int tfft_ragged_set_faults(tfft_ragged r, const tfft_fault *specs, int64_t n);
+
+/* Autotuner: for each length class, time the candidate plans (pass count,
+ * checksum group size, workgroups per launch) on the given buffers with
+ * fault tolerance CORRECT, `reps` executions each, and keep the fastest.
+ * Synchronous on hip_stream; invalidates captured graphs. */
+int tfft_ragged_tune(tfft_ragged r, const void *d_in, void *d_out, void *hip_stream, int reps);
+
+/* Classes of the ragged plan: their count in *classes and, for the first
+ * `cap` classes, length, number of signals and the chosen plan's
+ * description (arrays may be NULL). */
+int tfft_ragged_info(tfft_ragged r, int64_t *classes, int64_t *lengths, int64_t *counts, tfft_plan_desc *descs,
+                     int64_t cap);
 
 /* Static text for a status code. */
 const char *tfft_status_string(int status);

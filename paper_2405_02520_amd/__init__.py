@@ -40,7 +40,7 @@ _MODES = {"off": FT_OFF, "detect": FT_DETECT, "correct": FT_CORRECT}
 
 class tfft_options(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("group", ctypes.c_int32), ("kappa", ctypes.c_double),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("passes", ctypes.c_int32), ("grid_scale", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 MAX_PASSES = 3
@@ -91,6 +91,17 @@ _sig = {
     "tfft_plan_info": ([_P, ctypes.POINTER(tfft_plan_desc)], ctypes.c_int),
     "tfft_set_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "tfft_get_timings": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tfft_ragged_create": ([ctypes.POINTER(_P), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                            ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.POINTER(tfft_options)], ctypes.c_int),
+    "tfft_ragged_destroy": ([_P], ctypes.c_int),
+    "tfft_ragged_exec": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P], ctypes.c_int),
+    "tfft_ragged_get_report": ([_P, ctypes.POINTER(tfft_counts), ctypes.POINTER(tfft_record), ctypes.c_int64],
+                               ctypes.c_int),
+    "tfft_ragged_set_faults": ([_P, ctypes.POINTER(tfft_fault), ctypes.c_int64], ctypes.c_int),
+    "tfft_ragged_tune": ([_P, _P, _P, _P, ctypes.c_int], ctypes.c_int),
+    "tfft_ragged_info": ([_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(tfft_plan_desc), ctypes.c_int64],
+                         ctypes.c_int),
     "tfft_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "tfft_version": ([], ctypes.c_int),
 }
@@ -142,10 +153,11 @@ class Plan:
     """A plan for ``batch`` length-``n`` complex transforms on the current device."""
 
     def __init__(self, n: int, batch: int, dtype="c64", group: int = 0, kappa: float = 0.0,
-                 inverse_unscaled: bool = False):
+                 inverse_unscaled: bool = False, passes: int = 0, grid_scale: int = 0):
         self.n, self.batch = int(n), int(batch)
         self.dtype_code = _dtype_code(dtype)
-        opt = tfft_options(flags=INVERSE_UNSCALED if inverse_unscaled else 0, group=int(group), kappa=float(kappa))
+        opt = tfft_options(flags=INVERSE_UNSCALED if inverse_unscaled else 0, group=int(group), kappa=float(kappa),
+                           passes=int(passes), grid_scale=int(grid_scale))
         h = _P()
         _check(tfft_plan_create_with(ctypes.byref(h), self.n, self.batch, self.dtype_code, ctypes.byref(opt)),
                "tfft_plan_create_with")
@@ -176,12 +188,7 @@ class Plan:
     def info(self) -> dict:
         d = tfft_plan_desc()
         _check(tfft_plan_info(self._h, ctypes.byref(d)), "tfft_plan_info")
-        p = d.passes
-        return dict(n=d.n, batch=d.batch, dtype=d.dtype, passes=p, pass_len=list(d.pass_len[:p]),
-                    group=list(d.group[:p]), elems_per_thread=list(d.elems_per_thread[:p]),
-                    tile_signals=list(d.tile_signals[:p]), stages=list(d.stages[:p]),
-                    radices=[list(d.radices[i][:d.stages[i]]) for i in range(p)], groups=list(d.groups[:p]),
-                    workspace_bytes=int(d.workspace_bytes), kappa=d.kappa)
+        return _desc_dict(d)
 
     def _check_tensor(self, t, name):
         import torch
@@ -209,14 +216,8 @@ class Plan:
     def set_faults(self, faults):
         """faults: iterable of dicts with keys signal, pass_, stage, index and
         either value (complex, added) or flip ("re" | "im") with bit."""
-        faults = list(faults)
-        arr = (tfft_fault * max(1, len(faults)))()
-        for i, f in enumerate(faults):
-            v = complex(f.get("value", 0.0))
-            mode = {None: FAULT_ADD, "re": FAULT_FLIP_RE, "im": FAULT_FLIP_IM}[f.get("flip")]
-            arr[i] = tfft_fault(int(f["signal"]), int(f.get("pass_", 0)), int(f.get("stage", -1)),
-                                int(f["index"]), v.real, v.imag, mode, int(f.get("bit", 0)))
-        _check(tfft_set_faults(self._h, arr, len(faults)), "tfft_set_faults")
+        arr, n = _fault_array(faults)
+        _check(tfft_set_faults(self._h, arr, n), "tfft_set_faults")
 
     def set_timing(self, enable: bool = True):
         _check(tfft_set_timing(self._h, 1 if enable else 0), "tfft_set_timing")
@@ -231,16 +232,147 @@ class Plan:
 
     def report(self, cap: int | None = None):
         """(counts dict, [Record]) of the last execution; synchronises its stream."""
-        counts = tfft_counts()
-        st = tfft_get_report(self._h, ctypes.byref(counts), None, 0)
-        _check(st, "tfft_get_report")
-        n = counts.n_records if cap is None else min(cap, counts.n_records)
-        recs = (tfft_record * max(1, n))()
-        st = _check(tfft_get_report(self._h, ctypes.byref(counts), recs, n), "tfft_get_report")
-        self.last_status = st
-        if st == UNCORRECTABLE:
-            warnings.warn("tfft: a flagged checksum group could not be corrected", RuntimeWarning, stacklevel=2)
-        c = {k: getattr(counts, k) for k, _ in tfft_counts._fields_}
-        out = [Record(r.signal, r.sub, r.group, r.pass_, r.member, ACTION_NAMES.get(r.action, str(r.action)),
-                      r.method, r.residual, r.threshold, complex(r.ratio_re, r.ratio_im)) for r in recs[:n]]
+        c, out, self.last_status = _report(tfft_get_report, self._h, cap)
         return c, out
+
+
+def _fault_array(faults):
+    faults = list(faults)
+    arr = (tfft_fault * max(1, len(faults)))()
+    for i, f in enumerate(faults):
+        v = complex(f.get("value", 0.0))
+        mode = {None: FAULT_ADD, "re": FAULT_FLIP_RE, "im": FAULT_FLIP_IM}[f.get("flip")]
+        arr[i] = tfft_fault(int(f["signal"]), int(f.get("pass_", 0)), int(f.get("stage", -1)),
+                            int(f["index"]), v.real, v.imag, mode, int(f.get("bit", 0)))
+    return arr, len(faults)
+
+
+def _report(fn, h, cap):
+    counts = tfft_counts()
+    _check(fn(h, ctypes.byref(counts), None, 0), fn.__name__)
+    n = counts.n_records if cap is None else min(cap, counts.n_records)
+    recs = (tfft_record * max(1, n))()
+    st = _check(fn(h, ctypes.byref(counts), recs, n), fn.__name__)
+    if st == UNCORRECTABLE:
+        warnings.warn("tfft: a flagged checksum group could not be corrected", RuntimeWarning, stacklevel=3)
+    c = {k: getattr(counts, k) for k, _ in tfft_counts._fields_}
+    out = [Record(r.signal, r.sub, r.group, r.pass_, r.member, ACTION_NAMES.get(r.action, str(r.action)),
+                  r.method, r.residual, r.threshold, complex(r.ratio_re, r.ratio_im)) for r in recs[:n]]
+    return c, out, st
+
+
+class Ragged:
+    """Signals of mixed power-of-two lengths in one flat buffer: signal i is
+    elements [offsets[i], offsets[i] + lengths[i]) of the input and output
+    (default offsets: packed back to back).  Each length class runs as one
+    plan addressing its signals through a device offset table; ``use_graph``
+    replays all launches of all classes as one captured HIP graph."""
+
+    def __init__(self, lengths, offsets=None, dtype="c64", group: int = 0, kappa: float = 0.0):
+        import numpy as np
+        self.lengths = np.asarray(lengths, dtype=np.int64)
+        if offsets is None:
+            offsets = np.concatenate([[0], np.cumsum(self.lengths)[:-1]]) if len(self.lengths) else []
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.count = int(len(self.lengths))
+        self.extent = int((self.offsets + self.lengths).max()) if self.count else 0
+        self.dtype_code = _dtype_code(dtype)
+        opt = tfft_options(group=int(group), kappa=float(kappa))
+        ln = np.ascontiguousarray(self.lengths)
+        h = _P()
+        _check(tfft_ragged_create(ctypes.byref(h), self.count,
+                                  ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  self.dtype_code, ctypes.byref(opt)), "tfft_ragged_create")
+        self._h = h
+        self._gstream = None
+        self.last_status = OK
+
+    def close(self):
+        if getattr(self, "_h", None):
+            tfft_ragged_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_tensor(self, t, name):
+        import torch
+        want = torch.complex64 if self.dtype_code == C64 else torch.complex128
+        if not t.is_cuda or t.dtype != want or not t.is_contiguous() or t.numel() < self.extent:
+            raise ValueError(f"{name} must be a contiguous {want} CUDA tensor of at least {self.extent} elements")
+
+    def _stream(self, x, use_graph, stream):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(x.device)
+        if use_graph and st.cuda_stream == 0:
+            # graphs are captured on a stream of their own (the null stream cannot capture)
+            if self._gstream is None:
+                self._gstream = torch.cuda.Stream(x.device)
+            return st, self._gstream
+        return st, st
+
+    def execute(self, x, out=None, ft_mode="correct", inverse=False, use_graph=False, stream=None):
+        import torch
+        self._check_tensor(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_tensor(out, "output")
+        mode = _MODES[ft_mode] if isinstance(ft_mode, str) else int(ft_mode)
+        caller, st = self._stream(x, use_graph, stream)
+        if st is not caller:
+            st.wait_stream(caller)
+        _check(tfft_ragged_exec(self._h, x.data_ptr(), out.data_ptr(), mode, 1 if inverse else 0,
+                                1 if use_graph else 0, st.cuda_stream), "tfft_ragged_exec")
+        if st is not caller:
+            caller.wait_stream(st)
+            x.record_stream(st)
+            out.record_stream(st)
+        return out
+
+    def forward(self, x, out=None, ft_mode="correct", use_graph=False, stream=None):
+        return self.execute(x, out, ft_mode, False, use_graph, stream)
+
+    def inverse(self, x, out=None, ft_mode="correct", use_graph=False, stream=None):
+        return self.execute(x, out, ft_mode, True, use_graph, stream)
+
+    def set_faults(self, faults):
+        """As Plan.set_faults, with ``signal`` the ragged index."""
+        arr, n = _fault_array(faults)
+        _check(tfft_ragged_set_faults(self._h, arr, n), "tfft_ragged_set_faults")
+
+    def tune(self, x, out, reps: int = 3, stream=None):
+        import torch
+        self._check_tensor(x, "input")
+        self._check_tensor(out, "output")
+        st = stream if stream is not None else torch.cuda.current_stream(x.device)
+        _check(tfft_ragged_tune(self._h, x.data_ptr(), out.data_ptr(), st.cuda_stream, int(reps)),
+               "tfft_ragged_tune")
+
+    def info(self):
+        """[(length, signals, plan description dict)] per length class."""
+        nc = ctypes.c_int64()
+        _check(tfft_ragged_info(self._h, ctypes.byref(nc), None, None, None, 0), "tfft_ragged_info")
+        k = nc.value
+        ln = (ctypes.c_int64 * max(1, k))()
+        cn = (ctypes.c_int64 * max(1, k))()
+        ds = (tfft_plan_desc * max(1, k))()
+        _check(tfft_ragged_info(self._h, ctypes.byref(nc), ln, cn, ds, k), "tfft_ragged_info")
+        return [(int(ln[i]), int(cn[i]), _desc_dict(ds[i])) for i in range(k)]
+
+    def report(self, cap: int | None = None):
+        """Merged (counts dict, [Record]) of the last execution; records carry the ragged index."""
+        c, out, self.last_status = _report(tfft_ragged_get_report, self._h, cap)
+        return c, out
+
+
+def _desc_dict(d) -> dict:
+    p = d.passes
+    return dict(n=d.n, batch=d.batch, dtype=d.dtype, passes=p, pass_len=list(d.pass_len[:p]),
+                group=list(d.group[:p]), elems_per_thread=list(d.elems_per_thread[:p]),
+                tile_signals=list(d.tile_signals[:p]), stages=list(d.stages[:p]),
+                radices=[list(d.radices[i][:d.stages[i]]) for i in range(p)], groups=list(d.groups[:p]),
+                workspace_bytes=int(d.workspace_bytes), kappa=d.kappa)

@@ -165,6 +165,9 @@ struct PassArgs {
     int64_t rec_cap;
     const int32_t *fault_head; // [n_groups] first fault of each group or -1; NULL if none
     const DevFault *faults;
+    // element offset of each signal in the input / output buffer (ragged
+    // batches); NULL: signal b starts at b * N
+    const int64_t *in_sig, *out_sig;
 };
 
 // Host-side launchers (defined in the kernel translation unit).

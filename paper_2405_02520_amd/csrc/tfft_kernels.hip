@@ -178,8 +178,9 @@ __device__ __forceinline__ MemberLoc member_loc(const PassArgs &a, int64_t g, in
     if constexpr (KIND == KIND_ROWS) {
         const int64_t s = g * a.G + b;
         L.valid = s < a.batch;
-        L.in_off = s * M;
-        L.out_off = s * M;
+        const int64_t sc = L.valid ? s : 0;
+        L.in_off = a.in_sig ? a.in_sig[sc] : s * M;
+        L.out_off = a.out_sig ? a.out_sig[sc] : s * M;
         L.in_stride = 1;
         L.out_stride = 1;
         L.tw_i = 0;
@@ -189,16 +190,17 @@ __device__ __forceinline__ MemberLoc member_loc(const PassArgs &a, int64_t g, in
         const int64_t r = strip * C + b % C;                 // sub-signal inside the unit
         L.valid = u < a.n_outer;
         if constexpr (KIND == KIND_STRIDED) {
-            const int64_t beta = u / a.O, o = u % a.O;
-            L.in_off = beta * a.n + o * a.L + r;
-            L.out_off = L.in_off;
+            const int64_t beta = L.valid ? u / a.O : 0, o = u % a.O;
+            L.in_off = (a.in_sig ? a.in_sig[beta] : beta * a.n) + o * a.L + r;
+            L.out_off = (a.out_sig ? a.out_sig[beta] : beta * a.n) + o * a.L + r;
             L.in_stride = (uint32_t)a.S;
             L.out_stride = (uint32_t)a.S;
             L.tw_i = r;
         } else {
             const int64_t o = (r % a.m1) * a.m2 + r / a.m1;
-            L.in_off = u * a.n + o * M;
-            L.out_off = u * a.n + r;
+            const int64_t beta = L.valid ? u : 0;
+            L.in_off = (a.in_sig ? a.in_sig[beta] : u * a.n) + o * M;
+            L.out_off = (a.out_sig ? a.out_sig[beta] : u * a.n) + r;
             L.in_stride = 1;
             L.out_stride = (uint32_t)a.rows;
             L.tw_i = 0;

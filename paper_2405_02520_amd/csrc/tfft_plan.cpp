@@ -95,6 +95,8 @@ struct tfft_plan_s {
     int executed = 0;
     int last_mode = 0;
     int64_t nfaults = 0;
+    int64_t *d_sig_off = nullptr;  // ragged class: element offset of each signal (device)
+    int64_t extent = 0;            // elements spanned by the input / output buffers
     int timing = 0;              // record events around each launch
     int timed_last = 0;          // the last execution was timed
     hipEvent_t ev[2 * kMaxPasses + 1] = {};
@@ -146,7 +148,7 @@ std::vector<double> checksum_vec(int M, bool inverse, double scale) {
     return out;
 }
 
-int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser) {
+int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser, int grid_scale) {
     PassPlan &P = p->pass[idx];
     const int fp64 = p->dtype == TFFT_C128;
     P.M = M;
@@ -193,6 +195,8 @@ int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser) {
         const int occ = std::max(1, pass_occupancy(fp64, M, kind, 1));
         cap = std::max<int64_t>(8, (int64_t)TFFT_GRID_MULT * occ * std::max(1, cus));
     }
+    if (grid_scale > 0) cap <<= grid_scale;
+    if (grid_scale < 0) cap = std::max<int64_t>(8, cap >> (-grid_scale));
     int64_t grid = std::min<int64_t>(P.n_groups, cap);
     if (grid >= 8) grid = (grid + 7) / 8 * 8;
     P.grid = (int)std::max<int64_t>(1, grid);
@@ -240,6 +244,7 @@ void free_plan(tfft_plan_s *p) {
     (void)hipFree(p->d_work);
     (void)hipFree(p->d_rep);
     (void)hipFree(p->d_recs);
+    (void)hipFree(p->d_sig_off);
     for (auto &e : p->ev)
         if (e) (void)hipEventDestroy(e);
     (void)hipSetDevice(cur);
@@ -275,7 +280,7 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
     if (mode < TFFT_FT_OFF || mode > TFFT_FT_CORRECT) return TFFT_E_INVALID;
     if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 15)) return TFFT_E_INVALID;
     const size_t esz = p->dtype == TFFT_C128 ? 16 : 8;
-    const size_t bytes = (size_t)p->n * (size_t)p->batch * esz;
+    const size_t bytes = (size_t)p->extent * esz;
     const uintptr_t a = (uintptr_t)d_in, b = (uintptr_t)d_out;
     if ((a < b ? b - a : a - b) < bytes) return TFFT_E_INVALID;
     Guard guard(p->device);
@@ -313,6 +318,10 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
         A.m2 = P.m2;
         A.tw_scale = P.tw_scale;
         A.n_outer = P.n_outer;
+        // ragged classes address their signals through the offset table in
+        // the user buffers; the workspace is always dense [batch][n]
+        A.in_sig = (A.in == d_in || A.in == (const void *)d_out) ? p->d_sig_off : nullptr;
+        A.out_sig = (A.out == d_out) ? p->d_sig_off : nullptr;
         A.G = P.G;
         A.rb = P.rb;
         A.n_strips = P.n_strips;
@@ -370,7 +379,15 @@ const char *tfft_status_string(int s) {
     }
 }
 
-int tfft_plan_create_with(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_options *opt) {
+}  // extern "C"
+
+namespace {
+
+// Plan construction shared by dense and ragged plans.  host_off (may be
+// NULL): element offsets of the `batch` signals inside buffers spanning
+// `extent` elements.
+int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_options *opt, const int64_t *host_off,
+                int64_t extent) {
     if (!out) return TFFT_E_INVALID;
     *out = nullptr;
     if (n < 2 || n > (int64_t(1) << 24) || (n & (n - 1)) != 0) return TFFT_E_INVALID;
@@ -382,6 +399,15 @@ int tfft_plan_create_with(tfft_plan *out, int64_t n, int64_t batch, int dtype, c
     if (Guser < 0 || Guser > 64 || (Guser & (Guser - 1)) != 0) return TFFT_E_INVALID;
     if (opt && (opt->kappa < 0 || !std::isfinite(opt->kappa))) return TFFT_E_INVALID;
     if (flags & ~(uint32_t)TFFT_INVERSE_UNSCALED) return TFFT_E_INVALID;
+    const int force_passes = opt ? opt->passes : 0;
+    const int grid_scale = opt ? opt->grid_scale : 0;
+    if (force_passes < 0 || force_passes > 3 || grid_scale < -3 || grid_scale > 3) return TFFT_E_INVALID;
+    {
+        const int kk = ilog2_64(n);
+        if ((force_passes == 1 && kk > 12) || (force_passes == 2 && (kk < 8 || kk > 20)) ||
+            (force_passes == 3 && kk < 12))
+            return TFFT_E_UNSUPPORTED;
+    }
 
     tfft_plan_s *p = new (std::nothrow) tfft_plan_s();
     if (!p) return TFFT_E_NOMEM;
@@ -391,15 +417,17 @@ int tfft_plan_create_with(tfft_plan *out, int64_t n, int64_t batch, int dtype, c
     p->dtype = dtype;
     p->flags = flags;
     p->kappa = (opt && opt->kappa > 0) ? opt->kappa : 16.0;
+    p->extent = host_off ? extent : n * batch;
     const int k = ilog2_64(n);
     int rc = TFFT_OK;
     // one pass up to 2^12; two passes up to 2^TFFT_TWO_PASS_MAX_LOG2; three
     // passes above, the shortest first (tiles of the strided passes then hold
     // >= 16 adjacent sub-signals, i.e. >= 128-byte segments per row)
-    if (k <= 12) {
+    const int npass = force_passes ? force_passes : (k <= 12 ? 1 : (k <= TFFT_TWO_PASS_MAX_LOG2 ? 2 : 3));
+    if (npass == 1) {
         p->passes = 1;
         p->lens[0] = (int)n;
-    } else if (k <= TFFT_TWO_PASS_MAX_LOG2) {
+    } else if (npass == 2) {
         p->passes = 2;
         p->lens[0] = 1 << (k / 2);
         p->lens[1] = 1 << (k - k / 2);
@@ -412,7 +440,7 @@ int tfft_plan_create_with(tfft_plan *out, int64_t n, int64_t batch, int dtype, c
     }
     for (int i = 0; i < p->passes && rc == TFFT_OK; ++i) {
         const int kind = p->passes == 1 ? KIND_ROWS : (i == p->passes - 1 ? KIND_LAST : KIND_STRIDED);
-        rc = build_pass(p, i, p->lens[i], kind, Guser);
+        rc = build_pass(p, i, p->lens[i], kind, Guser, grid_scale);
     }
     if (rc == TFFT_OK && p->passes > 1) {
         // w_N^t = lo[t mod 2^b] * hi[t >> b]
@@ -449,12 +477,24 @@ int tfft_plan_create_with(tfft_plan *out, int64_t n, int64_t batch, int dtype, c
         else if (hipMemset(p->d_rep, 0, sizeof(DevReport)) != hipSuccess)
             rc = TFFT_E_HIP;
     }
+    if (rc == TFFT_OK && host_off) {
+        std::vector<int64_t> off(host_off, host_off + batch);
+        rc = upload(&p->d_sig_off, off);
+    }
     if (rc != TFFT_OK) {
         free_plan(p);
         return rc;
     }
     *out = p;
     return TFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tfft_plan_create_with(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_options *opt) {
+    return create_plan(out, n, batch, dtype, opt, nullptr, 0);
 }
 
 int tfft_plan_create(tfft_plan *out, int64_t n, int64_t batch, int dtype, uint32_t flags) {
@@ -641,6 +681,288 @@ int tfft_get_timings(tfft_plan p, double *pass_ms, double *correct_ms) {
         }
         if (pass_ms) pass_ms[i] = a;
         if (correct_ms) correct_ms[i] = p->launched_correct ? b : 0.0;
+    }
+    return TFFT_OK;
+}
+
+}  // extern "C"
+
+struct tfft_ragged_s {
+    int device = 0;
+    int dtype = 0;
+    tfft_options opt{};
+    int64_t count = 0, extent = 0;
+    std::vector<int64_t> lengths, offsets;
+    struct Class {
+        int64_t n = 0;
+        std::vector<int64_t> members;  // ragged indices of its signals
+        tfft_plan plan = nullptr;
+    };
+    std::vector<Class> classes;
+    std::vector<int64_t> class_of, local_of;
+    // captured graph and its key
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void *g_in = nullptr;
+    void *g_out = nullptr;
+    int g_mode = -1, g_inv = -1;
+    hipStream_t g_stream = nullptr;
+    hipStream_t last_stream = nullptr;
+    int executed = 0, last_mode = 0;
+};
+
+namespace {
+
+void drop_graph(tfft_ragged_s *r) {
+    if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
+    if (r->graph) (void)hipGraphDestroy(r->graph);
+    r->gexec = nullptr;
+    r->graph = nullptr;
+    r->g_in = nullptr;
+    r->g_out = nullptr;
+}
+
+int build_class(tfft_ragged_s *r, size_t ci, const tfft_options &opt) {
+    auto &C = r->classes[ci];
+    std::vector<int64_t> off;
+    off.reserve(C.members.size());
+    for (int64_t i : C.members) off.push_back(r->offsets[(size_t)i]);
+    tfft_plan np = nullptr;
+    const int rc = create_plan(&np, C.n, (int64_t)C.members.size(), r->dtype, &opt, off.data(), r->extent);
+    if (rc != TFFT_OK) return rc;
+    if (C.plan) tfft_plan_destroy(C.plan);
+    C.plan = np;
+    return TFFT_OK;
+}
+
+int ragged_launch(tfft_ragged_s *r, const void *d_in, void *d_out, int ft_mode, int inverse, hipStream_t st) {
+    for (auto &C : r->classes) {
+        const int rc = exec(C.plan, d_in, d_out, ft_mode, st, inverse != 0);
+        if (rc != TFFT_OK) return rc;
+    }
+    return TFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tfft_ragged_create(tfft_ragged *out, int64_t count, const int64_t *lengths, const int64_t *offsets, int dtype,
+                       const tfft_options *opt) {
+    if (!out) return TFFT_E_INVALID;
+    *out = nullptr;
+    if (count < 1 || !lengths || !offsets || dtype < TFFT_C64 || dtype > TFFT_C128) return TFFT_E_INVALID;
+    int64_t extent = 0;
+    std::vector<std::pair<int64_t, int64_t>> spans((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t n = lengths[i], o = offsets[i];
+        if (n < 2 || n > (int64_t(1) << 24) || (n & (n - 1)) != 0 || o < 0 || o > (int64_t(1) << 40))
+            return TFFT_E_INVALID;
+        spans[(size_t)i] = {o, o + n};
+        extent = std::max(extent, o + n);
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second) return TFFT_E_INVALID;  // signals overlap
+    tfft_ragged_s *r = new (std::nothrow) tfft_ragged_s();
+    if (!r) return TFFT_E_NOMEM;
+    (void)hipGetDevice(&r->device);
+    r->dtype = dtype;
+    if (opt) r->opt = *opt;
+    r->count = count;
+    r->extent = extent;
+    r->lengths.assign(lengths, lengths + count);
+    r->offsets.assign(offsets, offsets + count);
+    r->class_of.resize((size_t)count);
+    r->local_of.resize((size_t)count);
+    std::vector<int64_t> ns(r->lengths);
+    std::sort(ns.begin(), ns.end());
+    ns.erase(std::unique(ns.begin(), ns.end()), ns.end());
+    r->classes.resize(ns.size());
+    for (size_t c = 0; c < ns.size(); ++c) r->classes[c].n = ns[c];
+    for (int64_t i = 0; i < count; ++i) {
+        const size_t c = (size_t)(std::lower_bound(ns.begin(), ns.end(), r->lengths[(size_t)i]) - ns.begin());
+        r->class_of[(size_t)i] = (int64_t)c;
+        r->local_of[(size_t)i] = (int64_t)r->classes[c].members.size();
+        r->classes[c].members.push_back(i);
+    }
+    for (size_t c = 0; c < r->classes.size(); ++c) {
+        const int rc = build_class(r, c, r->opt);
+        if (rc != TFFT_OK) {
+            tfft_ragged_destroy(r);
+            return rc;
+        }
+    }
+    *out = r;
+    return TFFT_OK;
+}
+
+int tfft_ragged_destroy(tfft_ragged r) {
+    if (!r) return TFFT_OK;
+    Guard guard(r->device);
+    drop_graph(r);
+    for (auto &C : r->classes) tfft_plan_destroy(C.plan);
+    delete r;
+    return TFFT_OK;
+}
+
+int tfft_ragged_exec(tfft_ragged r, const void *d_in, void *d_out, int ft_mode, int inverse, int use_graph,
+                     void *hip_stream) {
+    if (!r || !d_in || !d_out) return TFFT_E_INVALID;
+    if (use_graph && !hip_stream) return TFFT_E_INVALID;
+    Guard guard(r->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    int rc;
+    if (!use_graph) {
+        rc = ragged_launch(r, d_in, d_out, ft_mode, inverse, st);
+    } else {
+        if (!(r->gexec && r->g_in == d_in && r->g_out == d_out && r->g_mode == ft_mode && r->g_inv == inverse &&
+              r->g_stream == st)) {
+            drop_graph(r);
+            for (auto &C : r->classes) C.plan->timing = 0;  // no event nodes in the graph
+            if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return TFFT_E_HIP;
+            rc = ragged_launch(r, d_in, d_out, ft_mode, inverse, st);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(st, &g);
+            if (rc != TFFT_OK || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc != TFFT_OK ? rc : TFFT_E_HIP;
+            }
+            r->graph = g;
+            if (hipGraphInstantiate(&r->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+                drop_graph(r);
+                return TFFT_E_HIP;
+            }
+            r->g_in = d_in;
+            r->g_out = d_out;
+            r->g_mode = ft_mode;
+            r->g_inv = inverse;
+            r->g_stream = st;
+        }
+        rc = hipGraphLaunch(r->gexec, st) == hipSuccess ? TFFT_OK : TFFT_E_HIP;
+        for (auto &C : r->classes) {
+            C.plan->executed = 1;
+            C.plan->last_mode = ft_mode;
+            C.plan->last_stream = st;
+            C.plan->timed_last = 0;
+            C.plan->launched_correct = ft_mode == TFFT_FT_CORRECT;
+        }
+    }
+    if (rc == TFFT_OK) {
+        r->executed = 1;
+        r->last_mode = ft_mode;
+        r->last_stream = st;
+    }
+    return rc;
+}
+
+int tfft_ragged_get_report(tfft_ragged r, tfft_counts *counts, tfft_record *recs, int64_t cap) {
+    if (!r || cap < 0 || (cap > 0 && !recs)) return TFFT_E_INVALID;
+    if (!r->executed) return TFFT_E_STATE;
+    Guard guard(r->device);
+    if (hipStreamSynchronize(r->last_stream) != hipSuccess) return TFFT_E_HIP;
+    tfft_counts total;
+    std::memset(&total, 0, sizeof(total));
+    int status = TFFT_OK;
+    int64_t filled = 0;
+    for (auto &C : r->classes) {
+        tfft_counts c;
+        int rc = tfft_get_report(C.plan, &c, nullptr, 0);
+        if (rc < 0) return rc;
+        std::vector<tfft_record> v((size_t)c.n_records);
+        rc = tfft_get_report(C.plan, &c, v.data(), c.n_records);
+        if (rc < 0) return rc;
+        if (rc == TFFT_UNCORRECTABLE) status = TFFT_UNCORRECTABLE;
+        total.groups_checked += c.groups_checked;
+        total.detected += c.detected;
+        total.corrected += c.corrected;
+        total.uncorrectable += c.uncorrectable;
+        total.benign += c.benign;
+        total.n_records += c.n_records;
+        total.dropped += c.dropped;
+        for (auto &x : v) {
+            if (filled >= cap) break;
+            x.signal = C.members[(size_t)x.signal];
+            recs[filled++] = x;
+        }
+    }
+    if (counts) *counts = total;
+    return status;
+}
+
+int tfft_ragged_set_faults(tfft_ragged r, const tfft_fault *specs, int64_t n) {
+    if (!r || n < 0 || (n > 0 && !specs)) return TFFT_E_INVALID;
+    std::vector<std::vector<tfft_fault>> per(r->classes.size());
+    for (int64_t k = 0; k < n; ++k) {
+        if (specs[k].signal < 0 || specs[k].signal >= r->count) return TFFT_E_INVALID;
+        tfft_fault f = specs[k];
+        const size_t c = (size_t)r->class_of[(size_t)f.signal];
+        f.signal = r->local_of[(size_t)f.signal];
+        per[c].push_back(f);
+    }
+    drop_graph(r);
+    for (size_t c = 0; c < r->classes.size(); ++c) {
+        const int rc = tfft_set_faults(r->classes[c].plan, per[c].data(), (int64_t)per[c].size());
+        if (rc != TFFT_OK) return rc;
+    }
+    return TFFT_OK;
+}
+
+int tfft_ragged_tune(tfft_ragged r, const void *d_in, void *d_out, void *hip_stream, int reps) {
+    if (!r || !d_in || !d_out || reps < 1) return TFFT_E_INVALID;
+    Guard guard(r->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    drop_graph(r);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TFFT_E_HIP;
+    int status = TFFT_OK;
+    for (size_t ci = 0; ci < r->classes.size() && status == TFFT_OK; ++ci) {
+        auto &C = r->classes[ci];
+        const int k = ilog2_64(C.n);
+        // candidates: pass count, checksum group size, workgroups per launch
+        std::vector<tfft_options> cand;
+        for (int ps = 1; ps <= 3; ++ps) {
+            if ((ps == 1 && k > 12) || (ps == 2 && (k < 8 || k > 20)) || (ps == 3 && k < 12)) continue;
+            for (int grp : {0, 16, 64})
+                for (int gs : {-1, 0, 1}) {
+                    tfft_options o = r->opt;
+                    o.passes = ps;
+                    o.group = grp;
+                    o.grid_scale = gs;
+                    cand.push_back(o);
+                }
+        }
+        float best = 1e30f;
+        tfft_options best_opt = r->opt;
+        for (const auto &o : cand) {
+            if (build_class(r, ci, o) != TFFT_OK) continue;  // unsupported candidate
+            float ms = 0.f;
+            bool ok = true;
+            for (int t = 0; t <= reps && ok; ++t) {  // first run warms up
+                if (t == 1 && hipEventRecord(e0, st) != hipSuccess) ok = false;
+                if (exec(C.plan, d_in, d_out, TFFT_FT_CORRECT, st, false) != TFFT_OK) ok = false;
+            }
+            if (ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ok && ms < best) {
+                best = ms;
+                best_opt = o;
+            }
+        }
+        status = build_class(r, ci, best_opt);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return status;
+}
+
+int tfft_ragged_info(tfft_ragged r, int64_t *classes, int64_t *lengths, int64_t *counts, tfft_plan_desc *descs,
+                     int64_t cap) {
+    if (!r || cap < 0) return TFFT_E_INVALID;
+    if (classes) *classes = (int64_t)r->classes.size();
+    for (int64_t c = 0; c < std::min<int64_t>(cap, (int64_t)r->classes.size()); ++c) {
+        if (lengths) lengths[c] = r->classes[(size_t)c].n;
+        if (counts) counts[c] = (int64_t)r->classes[(size_t)c].members.size();
+        if (descs) tfft_plan_info(r->classes[(size_t)c].plan, &descs[c]);
     }
     return TFFT_OK;
 }

@@ -82,3 +82,50 @@ def test_record_layouts_match_header(tf):
     assert ctypes.sizeof(tf.tfft_record) == 8 * 3 + 4 * 4 + 8 * 4
     assert ctypes.sizeof(tf.tfft_fault) == 8 + 4 + 4 + 8 + 16 + 8
     assert ctypes.sizeof(tf.tfft_counts) == 7 * 8
+
+
+def test_options_layout_and_pass_forcing(tf):
+    assert ctypes.sizeof(tf.tfft_options) == 4 + 4 + 8 + 4 + 4 + 6 * 4
+    h = ctypes.c_void_p()
+    for passes, grid_scale in [(4, 0), (-1, 0), (0, 4), (0, -4)]:
+        opt = tf.tfft_options(passes=passes, grid_scale=grid_scale)
+        assert tf.tfft_plan_create_with(ctypes.byref(h), 1024, 4, 0, ctypes.byref(opt)) == tf.E_INVALID
+    # pass counts outside what the decomposition supports for that length
+    for n, passes in [(1 << 13, 1), (1 << 7, 2), (1 << 21, 2), (1 << 11, 3)]:
+        opt = tf.tfft_options(passes=passes)
+        assert tf.tfft_plan_create_with(ctypes.byref(h), n, 4, 0, ctypes.byref(opt)) == tf.E_UNSUPPORTED
+    assert not h.value
+
+
+def _ragged_create(tf, lengths, offsets, dtype=0):
+    h = ctypes.c_void_p(1234)
+    L = (ctypes.c_int64 * max(1, len(lengths)))(*lengths)
+    O = (ctypes.c_int64 * max(1, len(offsets)))(*offsets)
+    st = tf.tfft_ragged_create(ctypes.byref(h), len(lengths), L, O, dtype, None)
+    return st, h
+
+
+@pytest.mark.parametrize("lengths,offsets,dtype", [
+    ([], [], 0),                      # no signals
+    ([64, 48], [0, 64], 0),           # not a power of two
+    ([64, 1], [0, 64], 0),            # shorter than 2
+    ([64, 1 << 25], [0, 64], 0),      # longer than 2^24
+    ([64, 64], [0, -64], 0),          # negative offset
+    ([64, 64], [0, 32], 0),           # overlapping signals
+    ([64, 128], [100, 0], 0),         # overlapping, given out of order
+    ([64], [0], 2),                   # unknown dtype
+])
+def test_ragged_create_rejects_bad_arguments(tf, lengths, offsets, dtype):
+    st, h = _ragged_create(tf, lengths, offsets, dtype)
+    assert st == tf.E_INVALID
+    assert not h.value
+
+
+def test_null_ragged_is_rejected(tf):
+    assert tf.tfft_ragged_destroy(None) == tf.OK
+    assert tf.tfft_ragged_exec(None, 16, 16, 0, 0, 0, None) == tf.E_INVALID
+    assert tf.tfft_ragged_get_report(None, None, None, 0) == tf.E_INVALID
+    assert tf.tfft_ragged_set_faults(None, None, 0) == tf.E_INVALID
+    assert tf.tfft_ragged_tune(None, 16, 16, None, 1) == tf.E_INVALID
+    assert tf.tfft_ragged_info(None, None, None, None, None, 0) == tf.E_INVALID
+    assert tf.tfft_ragged_create(None, 1, None, None, 0, None) == tf.E_INVALID

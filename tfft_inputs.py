@@ -78,3 +78,39 @@ def real_gaussian(seed: int, shape) -> np.ndarray:
     """Real N(0, 1) weights (float64), e.g. the fixed weights of the
     differentiable-layer loss sum |W * FFT(x)|^2."""
     return np.random.default_rng(seed).standard_normal(size=shape)
+
+
+def ragged_lengths(seed: int, count: int, kmin: int = 6, kmax: int = 20) -> np.ndarray:
+    """Signal lengths 2^k with k i.i.d. uniform on {kmin..kmax} (int64),
+    from ``default_rng(seed)``."""
+    k = np.random.default_rng(seed).integers(kmin, kmax + 1, size=count)
+    return (np.int64(1) << k.astype(np.int64)).astype(np.int64)
+
+
+def uniform_flat(seed: int, total: int, dtype=np.complex64) -> np.ndarray:
+    """A flat buffer of ``total`` values, re and im i.i.d. U[-1, 1) as in
+    ``uniform``, from ``default_rng(seed + 1)`` (so that one seed gives both
+    the lengths and the data)."""
+    rng = np.random.default_rng(seed + 1)
+    re = rng.uniform(-1.0, 1.0, size=total)
+    im = rng.uniform(-1.0, 1.0, size=total)
+    return _as_complex(re, im, dtype)
+
+
+def ragged_fault_signals(rng: np.random.Generator, lengths, nfaults: int, block: int = 64) -> np.ndarray:
+    """``nfaults`` distinct signal indices of a ragged batch, at most one in
+    each aligned block of ``block`` consecutive signals of one length
+    (counted in index order), so that no two land in one checksum group of
+    at most ``block`` signals: the one-fault-per-group model."""
+    lengths = np.asarray(lengths)
+    blocks: dict = {}
+    rank: dict = {}
+    for i, n in enumerate(lengths.tolist()):
+        r = rank.get(n, 0)
+        rank[n] = r + 1
+        blocks.setdefault((n, r // block), []).append(i)
+    keys = sorted(blocks)
+    if nfaults > len(keys):
+        raise ValueError(f"{nfaults} faults do not fit in {len(keys)} blocks")
+    pick = rng.choice(len(keys), size=nfaults, replace=False)
+    return np.sort(np.array([blocks[keys[k]][int(rng.integers(len(blocks[keys[k]])))] for k in pick], np.int64))
