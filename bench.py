@@ -51,10 +51,11 @@ def parse():
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("READS_DIR", "WRITE_DIR", "COPY_LOG2"),
                     help="turn rocprofv3 --pmc output directories (TCC_EA0_RDREQ_{32B,64B,128B}_sum, WRITE_SIZE) "
                          "of runs that included the copy calibration into profiles/pmc_traffic.json")
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "grad", "bitflip", "ragged"],
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "grad", "bitflip", "ragged", "schemes"],
                     help="sweep: the throughput sweep (default, the headline line); grad: the differentiable "
                          "layer, complex64 [2048, 4096] forward + backward; bitflip: the fault-coverage campaign; "
-                         "ragged: 4096 complex64 signals of lengths 2^U{6..20} in one graph launch")
+                         "ragged: 4096 complex64 signals of lengths 2^U{6..20} in one graph launch; schemes: checksum "
+                         "overhead of the block, one-sided and thread-level schemes, N = 2^8..2^12")
     ap.add_argument("--ft", default="correct", choices=["off", "detect", "correct"],
                     help="fault-tolerance mode of the timed workload (the headline uses correct)")
     return ap.parse_args()
@@ -266,8 +267,8 @@ def bench_ragged(args):
     tune_s = time.perf_counter() - t0
     rng = inputs.fault_rng(inputs.SEED_RAGGED)
     sigs = inputs.ragged_fault_signals(rng, lengths, count // 100)  # at most one per checksum group
-    rg.set_faults([dict(signal=int(s), stage=-1, index=int(rng.integers(lengths[s])),
-                        value=complex(rng.uniform(0.5, 4.0), rng.uniform(-4.0, 4.0))) for s in sigs])
+    faults = [dict(signal=int(s), stage=-1, index=int(rng.integers(lengths[s])),
+                   value=complex(rng.uniform(0.5, 4.0), rng.uniform(-4.0, 4.0))) for s in sigs]
 
     def timed(mode, graph):
         with torch.cuda.stream(st):
@@ -281,6 +282,8 @@ def bench_ragged(args):
         return (time.perf_counter() - t) * 1e3 / args.steps
 
     ms_off = timed("off", True)
+    ms_clean = timed("correct", True)
+    rg.set_faults(faults)
     ms_eager = timed("correct", False)
     ms = timed("correct", True)
     counts, _ = rg.report()
@@ -293,7 +296,9 @@ def bench_ragged(args):
            "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "dtype": "f32",
            "data": "synthetic: U[-1,1) complex", "effective_GBps": round(gbs, 1),
            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "ms_ft_off_graph": round(ms_off, 4),
-           "ms_ft_correct_eager": round(ms_eager, 4), "ft_overhead_pct": round((ms / ms_off - 1) * 100, 2),
+           "ms_ft_correct_eager": round(ms_eager, 4), "ms_ft_correct_no_faults": round(ms_clean, 4),
+           "ft_overhead_pct": round((ms_clean / ms_off - 1) * 100, 2),
+           "fault_overhead_pct": round((ms / ms_clean - 1) * 100, 2),
            "faults_injected": int(len(sigs)), "corrected": counts["corrected"],
            "uncorrectable": counts["uncorrectable"], "tune_s": round(tune_s, 2), "classes": classes,
            "config": {"workload": f"ragged: {count} complex64 signals, lengths 2^k with k ~ U{{6..20}} "
@@ -301,8 +306,59 @@ def bench_ragged(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_schemes(args):
+    """Checksum overhead by granularity (the comparison of one-sided,
+    thread-level two-sided and threadblock-level two-sided schemes): single-pass
+    sizes N = 2^8..2^12, 2^28 (complex64) / 2^27 (complex128) elements, FT
+    CORRECT without faults against FT OFF on the same kernels."""
+    import numpy as np
+    import torch
+
+    import paper_2405_02520_amd as tf
+    import tfft_inputs as inputs
+
+    st = torch.cuda.Stream()
+    rows = []
+    for dt in args.dtypes.split(","):
+        npdt = np.complex64 if dt == "c64" else np.complex128
+        total = 1 << (args.log2_elems - (0 if dt == "c64" else 1))
+        for k in range(max(8, args.kmin), min(12, args.kmax) + 1):
+            n = 1 << k
+            B = total // n
+            xd = torch.from_numpy(inputs.uniform(inputs.sweep_seed(k, dt == "c128"), B, n, npdt)).cuda()
+            out = torch.empty_like(xd)
+            ms = {}
+            for scheme in ("block", "signal", "thread"):
+                plan = tf.Plan(n, B, dt, scheme=scheme)
+                for mode in (["off"] if scheme == "block" else []) + ["correct"]:
+                    with torch.cuda.stream(st):
+                        for _ in range(max(1, args.warmup)):
+                            plan.forward(xd, out, ft_mode=mode)
+                        st.synchronize()
+                        t = time.perf_counter()
+                        for _ in range(args.steps):
+                            plan.forward(xd, out, ft_mode=mode)
+                        st.synchronize()
+                    ms["off" if mode == "off" else scheme] = (time.perf_counter() - t) * 1e3 / args.steps
+                counts, _ = plan.report()
+                assert counts["detected"] == 0, (dt, k, scheme, counts)
+                plan.close()
+            rows.append({"dtype": dt, "n": n, "batch": B, "ms_off": round(ms["off"], 4),
+                         **{f"overhead_pct_{s}": round((ms[s] / ms["off"] - 1) * 100, 2)
+                            for s in ("block", "signal", "thread")},
+                         "GBps_block": round(2 * total * (8 if dt == "c64" else 16) / (ms["block"] * 1e-3) / 1e9, 1)})
+            del xd, out
+    mean = {s: round(float(np.mean([r[f"overhead_pct_{s}"] for r in rows])), 2) for s in ("block", "signal", "thread")}
+    print(json.dumps({"metric": "checksum overhead % vs FT off, by scheme granularity", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "mean_overhead_pct": mean, "sizes": rows,
+                      "config": {"workload": "forward C2C, N = 2^8..2^12, N*batch = 2^28 (c64) / 2^27 (c128), "
+                                             "U[-1,1), FT correct without faults"}}), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "schemes":
+        return bench_schemes(args)
     if args.workload == "ragged":
         return bench_ragged(args)
     if args.workload == "grad":
@@ -424,7 +480,7 @@ def main():
     achieved = dalgo / (dms * 1e-3) / 1e9
     kind_code = {"rows": 0, "strided": 1, "last": 2}[dkind]
     kernel_key = (f"{ddt}_k{dk} void tfft::pass_kernel<{'float' if ddt == 'c64' else 'double'}, {dM}, {kind_code}, "
-                  f"{'false' if args.ft == 'off' else 'true'}>(tfft::PassArgs)")
+                  f"{0 if args.ft == 'off' else 1}>(tfft::PassArgs)")
     tr = pmc_traffic(kernel_key)
     if tr is not None:
         tr = tr["traffic_bytes"]

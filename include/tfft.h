@@ -73,8 +73,23 @@ enum tfft_action {
     TFFT_ACT_UNCORRECTABLE = 4  /* flagged, not locatable (outside one fault per group) */
 };
 
-/* Location method of a record. */
-enum tfft_locate { TFFT_LOC_NONE = 0, TFFT_LOC_QUOTIENT = 1, TFFT_LOC_PER_SIGNAL = 2 };
+/* Location method of a record.  TFFT_LOC_THREAD: the thread-level scheme
+ * found the fault inside one radix butterfly; record.sub then holds that
+ * butterfly's stage and the ratio is k + 1 for its wrong output k. */
+enum tfft_locate { TFFT_LOC_NONE = 0, TFFT_LOC_QUOTIENT = 1, TFFT_LOC_PER_SIGNAL = 2, TFFT_LOC_THREAD = 3 };
+
+/* Granularity of the checksum (TurboFFT Sec. IV-B and the overhead
+ * comparison of Sec. V).
+ *   BLOCK  - two-sided checksum over a group of G signals, one residual pair
+ *            per group reduced over the workgroup (the default);
+ *   SIGNAL - one-sided: one residual per signal (transform encoding only),
+ *            reduced over the signal's threads; a flagged signal is
+ *            recomputed in binary64;
+ *   THREAD - two-sided checks of every radix butterfly inside the thread that
+ *            computes it (two transform encodings e and (k+1) e locate the
+ *            wrong output); a flagged butterfly is recomputed in registers.
+ *            Protects the butterflies only, not the data between them. */
+enum tfft_scheme { TFFT_SCHEME_BLOCK = 0, TFFT_SCHEME_SIGNAL = 1, TFFT_SCHEME_THREAD = 2 };
 
 /* Options for tfft_plan_create_with.  Zero fields take the defaults. */
 typedef struct {
@@ -86,7 +101,8 @@ typedef struct {
                         length gives E_UNSUPPORTED */
     int32_t grid_scale; /* 0 = default; else workgroups per launch = default * 2^grid_scale
                            (-3..3), a tuning knob */
-    int32_t reserved[6];
+    int32_t scheme;  /* enum tfft_scheme; schemes other than BLOCK need n <= 2^12 (one pass) */
+    int32_t reserved[5];
 } tfft_options;
 
 /* Description of a plan (tfft_plan_info). */

@@ -21,6 +21,12 @@ writes out):
   residuals locates the corrupted signal; the divergence between the transform
   of the combined input, W (X w1), and the combined output, Y w1, is added
   back to it.
+* ``one_sided_signal`` -- the one-sided scheme (Section II-C per signal,
+  compared in Section V): the transform encoding of one signal, recomputed
+  when flagged.
+* ``butterfly_vectors``/``butterfly_check`` -- the thread-level two-sided
+  scheme (Section IV-B.1): each radix butterfly checked by two transform
+  encodings e and (k+1) e, the quotient locating the wrong output.
 * ``fourstep`` -- Section IV-A.1 (tiled FFT): a length N1*N2 transform as N2
   column transforms, a twiddle, and N1 row transforms whose outputs are stored
   transposed.  Used to state the per-pass checksum domains of a two-pass plan.
@@ -374,6 +380,70 @@ def two_sided_batch(X, Yhat, G: int, **kw):
         if rec.flagged:
             recs.append(rec)
     return out, recs
+
+
+# ------------------------------------------- one-sided and thread-level
+
+def one_sided_signal(x, yhat, *, inverse=False, scale=1.0, kappa=16.0, u=2.0 ** -24, mode="correct", signal=0):
+    """One-sided checksum of one signal (Section II-C, Eq. (1)-(2), and the
+    one-sided scheme of the overhead comparison in Section V): the transform
+    encoding alone, d1 = e^T yhat - (e^T W) x, tested against the threshold
+    of a group of one signal; a flagged signal is recomputed.
+
+    Returns (output, GroupRecord) with located = 0 when flagged."""
+    x = np.asarray(x, dtype=np.complex128)
+    y = np.array(yhat, dtype=np.complex128)
+    m = x.shape[-1]
+    e = encoding_vector(m)
+    c = checksum_vector(m, inverse, scale)
+    with np.errstate(all="ignore"):
+        d1 = complex(np.dot(e, y)) - complex(np.dot(c, x))
+    s_ = float(np.sum(x.real ** 2 + x.imag ** 2))
+    tau = threshold(m, s_, kappa, u) * abs(scale)
+    flagged = not (abs(d1) <= tau)
+    rec = GroupRecord(group=signal, flagged=flagged, d1=d1, d2=d1, tau=tau, s=s_, rho=complex(1.0))
+    if not flagged:
+        return y, rec
+    rec.located, rec.method = 0, "signal"
+    if mode == "detect":
+        rec.action = DETECTED
+        return y, rec
+    rec.action = CORRECTED
+    return fft(x, inverse=inverse, scale=scale), rec
+
+
+def butterfly_vectors(r: int) -> tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+    """The two transform encodings of a radix-r butterfly y = W_r v
+    (Section II-C applied to one butterfly): e_k = w_3^k and f_k = (k+1) e_k,
+    and their images c1 = W_r^T e, c2 = W_r^T f, as plain sums over the exact
+    twiddles.  Returns (e, f, c1, c2)."""
+    k = np.arange(r)
+    e = encoding_vector(r)
+    f = (k + 1) * e
+    W = omega(np.outer(k, k) % r, r)
+    return e, f, W.T @ e, W.T @ f
+
+
+def butterfly_check(v, y, *, kappa=16.0, u=2.0 ** -24):
+    """Thread-level two-sided check of one radix-r butterfly (Section IV-B.1:
+    the computation inside a thread protected by its own checksums).
+
+    v  [r] the butterfly's inputs (after their twiddles), y [r] its outputs as
+    produced.  d1 = e.y - c1.v and d2 = f.y - c2.v; flagged iff
+    !(|d1| <= tau) with tau the group threshold for m = r and S = |v|^2; a
+    single wrong output y_k gives d2/d1 = k + 1, accepted as for a group
+    quotient.  Returns (d1, d2, tau, flagged, k) with k = -1 when not located."""
+    v = np.asarray(v, dtype=np.complex128)
+    y = np.asarray(y, dtype=np.complex128)
+    r = v.shape[0]
+    e, f, c1, c2 = butterfly_vectors(r)
+    with np.errstate(all="ignore"):
+        d1 = complex(np.dot(e, y) - np.dot(c1, v))
+        d2 = complex(np.dot(f, y) - np.dot(c2, v))
+    tau = threshold(r, float(np.sum(v.real ** 2 + v.imag ** 2)), kappa, u)
+    flagged = not (abs(d1) <= tau)
+    k, _ = _locate_by_quotient(d1, d2, r)
+    return d1, d2, tau, flagged, k
 
 
 # ------------------------------------------------------------ four-step

@@ -32,7 +32,9 @@ OK, UNCORRECTABLE = 0, 1
 E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_STATE = -1, -2, -3, -4, -5
 INVERSE_UNSCALED = 1
 ACT_DETECTED, ACT_CORRECTED, ACT_BENIGN, ACT_UNCORRECTABLE = 1, 2, 3, 4
-LOC_NONE, LOC_QUOTIENT, LOC_PER_SIGNAL = 0, 1, 2
+LOC_NONE, LOC_QUOTIENT, LOC_PER_SIGNAL, LOC_THREAD = 0, 1, 2, 3
+SCHEME_BLOCK, SCHEME_SIGNAL, SCHEME_THREAD = 0, 1, 2
+_SCHEMES = {"block": SCHEME_BLOCK, "signal": SCHEME_SIGNAL, "thread": SCHEME_THREAD}
 ACTION_NAMES = {ACT_DETECTED: "detected", ACT_CORRECTED: "corrected", ACT_BENIGN: "benign",
                 ACT_UNCORRECTABLE: "uncorrectable"}
 _MODES = {"off": FT_OFF, "detect": FT_DETECT, "correct": FT_CORRECT}
@@ -40,7 +42,8 @@ _MODES = {"off": FT_OFF, "detect": FT_DETECT, "correct": FT_CORRECT}
 
 class tfft_options(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("group", ctypes.c_int32), ("kappa", ctypes.c_double),
-                ("passes", ctypes.c_int32), ("grid_scale", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("passes", ctypes.c_int32), ("grid_scale", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 MAX_PASSES = 3
@@ -153,11 +156,15 @@ class Plan:
     """A plan for ``batch`` length-``n`` complex transforms on the current device."""
 
     def __init__(self, n: int, batch: int, dtype="c64", group: int = 0, kappa: float = 0.0,
-                 inverse_unscaled: bool = False, passes: int = 0, grid_scale: int = 0):
+                 inverse_unscaled: bool = False, passes: int = 0, grid_scale: int = 0, scheme="block"):
+        """scheme: "block" (two-sided, per group of signals), "signal"
+        (one-sided, per signal) or "thread" (per radix butterfly); the last
+        two for n <= 4096."""
         self.n, self.batch = int(n), int(batch)
         self.dtype_code = _dtype_code(dtype)
+        sch = _SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         opt = tfft_options(flags=INVERSE_UNSCALED if inverse_unscaled else 0, group=int(group), kappa=float(kappa),
-                           passes=int(passes), grid_scale=int(grid_scale))
+                           passes=int(passes), grid_scale=int(grid_scale), scheme=sch)
         h = _P()
         _check(tfft_plan_create_with(ctypes.byref(h), self.n, self.batch, self.dtype_code, ctypes.byref(opt)),
                "tfft_plan_create_with")

@@ -96,6 +96,10 @@ constexpr int cfg_C(int fp64, int M, int kind) {
 #ifndef TFFT_TWO_PASS_MAX_LOG2
 #define TFFT_TWO_PASS_MAX_LOG2 18
 #endif
+// Parallel branches of a captured ragged graph (independent length classes).
+#ifndef TFFT_GRAPH_BRANCHES
+#define TFFT_GRAPH_BRANCHES 4
+#endif
 constexpr int cfg_twreg(int fp64, int M, int kind) { return fp64 ? TFFT_TWREG64 : TFFT_TWREG32; }
 constexpr int cfg_creg(int fp64, int M, int kind) { return fp64 ? TFFT_CREG64 : TFFT_CREG32; }
 // Issue the next tile's loads before transforming the current one.
@@ -168,7 +172,13 @@ struct PassArgs {
     // element offset of each signal in the input / output buffer (ragged
     // batches); NULL: signal b starts at b * N
     const int64_t *in_sig, *out_sig;
+    double kappa_u;     // FT_THREAD: kappa * unit roundoff (butterfly thresholds)
+    int32_t fix;        // FT_THREAD: recompute a flagged butterfly (CORRECT mode)
+    int32_t pad_;
 };
+
+// Checksum schemes of a pass kernel (template argument FT).
+enum { FT_NONE = 0, FT_BLOCK = 1, FT_SIGNAL = 2, FT_THREAD = 3 };
 
 // Host-side launchers (defined in the kernel translation unit).
 hipError_t launch_pass(int fp64, int M, int kind, int ft, const PassArgs &a, int grid, hipStream_t st);

@@ -332,10 +332,121 @@ struct Dpp32 {
 };
 
 // ------------------------------------------------------------- pass kernel
-template <typename R, int M, int KIND, bool FT>
+// cos(15 degrees * i), i = 0..23: the angles 2 pi t / (3 RAD) of the
+// butterfly encodings for RAD in {2, 4, 8} are multiples of 15 degrees.
+constexpr double kCos15[24] = {1.0, 0.96592582628906831, 0.86602540378443865, 0.70710678118654752, 0.5,
+                               0.25881904510252076, 0.0, -0.25881904510252076, -0.5, -0.70710678118654752,
+                               -0.86602540378443865, -0.96592582628906831, -1.0, -0.96592582628906831,
+                               -0.86602540378443865, -0.70710678118654752, -0.5, -0.25881904510252076, 0.0,
+                               0.25881904510252076, 0.5, 0.70710678118654752, 0.86602540378443865,
+                               0.96592582628906831};
+template <int RAD>
+constexpr double kCos3R(int t) { return kCos15[(t * (8 / RAD)) % 24]; }
+template <int RAD>
+constexpr double kSin3R(int t) { return kCos15[(t * (8 / RAD) + 18) % 24]; }
+
+// Two-sided check of one radix-RAD butterfly inside its thread (FT_THREAD).
+// The butterfly maps its (twiddled) inputs v to y = W_RAD v.  Transform
+// encodings e_k = w_3^k and (k+1) e_k on the outputs are compared with their
+// precomputed images c1 = W^T e and c2 = W^T ((k+1) e) applied to the inputs:
+// d1 = e.y - c1.v, d2 = ((k+1) e).y - c2.v.  A single wrong output y_k gives
+// d2 / d1 = k + 1; the butterfly is then recomputed from v (in CORRECT mode)
+// and the event recorded.  binary64 throughout; tau as for a group, with M =
+// RAD and S the energy of v.
+template <int RAD>
+struct ButterflyEnc {
+    double c1r[RAD], c1i[RAD], c2r[RAD], c2i[RAD];
+    constexpr ButterflyEnc() : c1r(), c1i(), c2r(), c2i() {
+        for (int q = 0; q < RAD; ++q) {
+            double ar = 0, ai = 0, br = 0, bi = 0;
+            for (int k = 0; k < RAD; ++k) {
+                // e_k w_RAD^{kq} = exp(-2 pi i (k/3 + kq/RAD)): angle index over 3 RAD
+                const int t = (k * RAD + 3 * k * q) % (3 * RAD);
+                const double cr = kCos3R<RAD>(t), ci = -kSin3R<RAD>(t);
+                ar += cr;
+                ai += ci;
+                br += (k + 1) * cr;
+                bi += (k + 1) * ci;
+            }
+            c1r[q] = ar;
+            c1i[q] = ai;
+            c2r[q] = br;
+            c2i[q] = bi;
+        }
+    }
+};
+
+template <typename R, int RAD, int NB, int P, int E>
+__device__ __forceinline__ void thread_check(cx<R> (&d)[E], const cx<R> (&vin)[E], const PassArgs &a, int64_t g,
+                                             int b, int s) {
+    constexpr ButterflyEnc<RAD> enc{};
+    double l1r = 0, l1i = 0, l2r = 0, l2i = 0, r1r = 0, r1i = 0, r2r = 0, r2i = 0, S = 0;
+#pragma unroll
+    for (int q = 0; q < RAD; ++q) {
+        const double vr = double(vin[P + q * NB].re), vi = double(vin[P + q * NB].im);
+        l1r += enc.c1r[q] * vr - enc.c1i[q] * vi;
+        l1i += enc.c1r[q] * vi + enc.c1i[q] * vr;
+        l2r += enc.c2r[q] * vr - enc.c2i[q] * vi;
+        l2i += enc.c2r[q] * vi + enc.c2i[q] * vr;
+        S += vr * vr + vi * vi;
+        // e_q = w_3^(q mod 3)
+        const double yr = double(d[P + q * NB].re), yi = double(d[P + q * NB].im);
+        const int cls = q % 3;
+        const double er = cls == 0 ? 1.0 : kW3r, ei = cls == 0 ? 0.0 : (cls == 1 ? kW3i : -kW3i);
+        const double tr = er * yr - ei * yi, ti = er * yi + ei * yr;
+        r1r += tr;
+        r1i += ti;
+        r2r += (q + 1) * tr;
+        r2i += (q + 1) * ti;
+    }
+    const double d1r = r1r - l1r, d1i = r1i - l1i, d2r = r2r - l2r, d2i = r2i - l2i;
+    constexpr double kLog = RAD == 2 ? 1.0 : (RAD == 4 ? 1.4142135623730951 : 1.7320508075688772);
+    const double tau = a.kappa_u * kLog * sqrt(double(RAD) * S);
+    if (!(sqrt(d1r * d1r + d1i * d1i) <= tau)) {
+        const double den = d1r * d1r + d1i * d1i;
+        const double rhor = (d2r * d1r + d2i * d1i) / den, rhoi = (d2i * d1r - d2r * d1i) / den;
+        if (a.fix) {
+            cx<R> v[RAD];
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) v[q] = vin[P + q * NB];
+            dft_small<R, RAD>(v);
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) d[P + q * NB] = v[q];
+            atomicAdd(&a.rep->corrected, 1ULL);
+        }
+        const unsigned long long slot = atomicAdd(&a.rep->n_flag, 1ULL);
+        if ((int64_t)slot < a.rec_cap) {
+            DevRecord rc;
+            rc.group = g;
+            rc.pass = a.pass;
+            rc.action = a.fix ? 2 : 1;  // corrected in registers, or detected
+            rc.member = b;
+            rc.method = 3;  // located inside the thread's butterfly
+            rc.d1r = d1r;
+            rc.d1i = d1i;
+            rc.d2r = d2r;
+            rc.d2i = d2i;
+            rc.tau = tau;
+            rc.s = double(s);
+            a.recs[slot] = rc;
+        }
+        (void)rhor;
+        (void)rhoi;
+    }
+}
+
+// FT selects the checksum scheme: FT_NONE (no checking), FT_BLOCK (two-sided,
+// one residual pair per group of G signals, reduced over the workgroup),
+// FT_SIGNAL (one-sided: one residual per signal, reduced over the signal's
+// threads; a flagged signal is recomputed) or FT_THREAD (two-sided checks of
+// every radix butterfly inside the thread that computes it, corrected in
+// registers).  FT_SIGNAL and FT_THREAD exist for single-pass plans.
+template <typename R, int M, int KIND, int FT>
 __global__ void __launch_bounds__(cfg_threads(sizeof(R) == 8, M, KIND))
 pass_kernel(PassArgs a) {
     constexpr int FP64 = sizeof(R) == 8;
+    constexpr bool BLK = FT == FT_BLOCK, SIG = FT == FT_SIGNAL, THR = FT == FT_THREAD;
+    constexpr bool ENC = BLK || SIG;  // input and output encodings
     constexpr int E = cfg_E(FP64, M);
     constexpr int T = M / E;
     constexpr int C = cfg_C(FP64, M, KIND);
@@ -366,7 +477,7 @@ pass_kernel(PassArgs a) {
     // the pre-transform checksum vector at positions j + T m: either kept in
     // registers for all signals of the workgroup or re-read per signal.
     constexpr bool TWREG = cfg_twreg(FP64, M, KIND) != 0;
-    constexpr bool CREG = FT && cfg_creg(FP64, M, KIND) != 0;
+    constexpr bool CREG = ENC && cfg_creg(FP64, M, KIND) != 0;
     const cx<R> *stw = reinterpret_cast<const cx<R> *>(a.stw);
     const cx<double> *cv = reinterpret_cast<const cx<double> *>(a.cvec);
     auto stage_tw = [&](auto S, auto p, auto q) -> cx<R> {
@@ -399,14 +510,20 @@ pass_kernel(PassArgs a) {
     int64_t wl = blockIdx.x;
     if (nwg % 8 == 0) wl = (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;  // XCD-contiguous group ranges
 
-    const int rounds = a.G / C;
+    // FT_SIGNAL: a tile of C signals per iteration, each its own group (G = 1)
+    const int rounds = SIG ? 1 : a.G / C;
+    const int64_t n_iter = SIG ? (a.n_groups + C - 1) / C : a.n_groups;
+    auto mloc = [&](int64_t gg, int rr) -> MemberLoc {
+        if constexpr (SIG) return member_loc<M, KIND, C>(a, gg * C + c, 0);
+        else return member_loc<M, KIND, C>(a, gg, rr * C + c);
+    };
     // Software pipeline: the loads of the next tile (next round, or round 0 of
     // this workgroup's next group) are issued before the current tile is
     // transformed, so every wavefront keeps two tiles of HBM reads in flight.
     cx<R> nx[E];
     auto load_tile = [&](int64_t gg, int rr) {
-        const MemberLoc Ln = member_loc<M, KIND, C>(a, gg, rr * C + c);
-        if (gg < a.n_groups && Ln.valid) {
+        const MemberLoc Ln = mloc(gg, rr);
+        if (gg < n_iter && Ln.valid) {
             const cx<R> *s = in + Ln.in_off;
 #pragma unroll
             for (int m = 0; m < E; ++m) nx[m] = ld_stream(s + (uint32_t)(j + T * m) * Ln.in_stride);
@@ -417,13 +534,16 @@ pass_kernel(PassArgs a) {
     };
     constexpr bool PREFETCH = cfg_prefetch(FP64, M, KIND) != 0;
     if constexpr (PREFETCH) load_tile(wl, 0);
-    for (int64_t g = wl; g < a.n_groups; g += nwg) {
-        const int fh = a.fault_head ? a.fault_head[g] : -1;
+    for (int64_t g = wl; g < n_iter; g += nwg) {
+        const int64_t gsig = g * C + c;  // FT_SIGNAL: this thread's signal (= its group)
+        int fh;
+        if constexpr (SIG) fh = (a.fault_head && gsig < a.n_groups) ? a.fault_head[gsig] : -1;
+        else fh = a.fault_head ? a.fault_head[g] : -1;
         double D1r = 0.0, D1i = 0.0, D2r = 0.0, D2i = 0.0;
         R Ssum = R(0);  // energy of the group's inputs, for the threshold only
         for (int r = 0; r < rounds; ++r) {
-            const int b = r * C + c;
-            const MemberLoc L = member_loc<M, KIND, C>(a, g, b);
+            const int b = SIG ? 0 : r * C + c;
+            const MemberLoc L = mloc(g, r);
             // offsets inside one signal are below N <= 2^24: 32-bit arithmetic
             cx<R> *dst = out + L.out_off;
             const uint32_t ostr = (uint32_t)L.out_stride;
@@ -438,7 +558,7 @@ pass_kernel(PassArgs a) {
 #pragma unroll
                 for (int m = 0; m < E; ++m) d[m] = nx[m];
             }
-            if constexpr (FT) {
+            if constexpr (ENC) {
                 double lr = 0.0, li = 0.0;
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
@@ -450,11 +570,13 @@ pass_kernel(PassArgs a) {
                     li += cm.re * xi + cm.im * xr;
                     Ssum += d[m].re * d[m].re + d[m].im * d[m].im;
                 }
-                const double w2 = double(b + 1);
                 D1r -= lr;
                 D1i -= li;
-                D2r -= w2 * lr;
-                D2i -= w2 * li;
+                if constexpr (BLK) {
+                    const double w2 = double(b + 1);
+                    D2r -= w2 * lr;
+                    D2i -= w2 * li;
+                }
             }
             if (a.conj_in) {
 #pragma unroll
@@ -477,13 +599,29 @@ pass_kernel(PassArgs a) {
                         });
                     });
                 }
+                cx<R> vin[THR ? E : 1];  // FT_THREAD: the butterflies' inputs
+                if constexpr (THR) {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) vin[m] = d[m];
+                }
                 static_for<0, NB>([&](auto p) {
                     cx<R> v[RAD];
                     static_for<0, RAD>([&](auto q) { v[q] = d[p + q * NB]; });
                     dft_small<R, RAD>(v);
                     static_for<0, RAD>([&](auto q) { d[p + q * NB] = v[q]; });
                 });
-                if (fh >= 0) apply_faults<R, E>(d, a.faults, fh, s, b, j);
+                if (fh >= 0) {
+                    apply_faults<R, E>(d, a.faults, fh, s, b, j);
+                    // FT_THREAD has no output encoding: a fault on a final
+                    // value lands on the last butterfly's output
+                    if constexpr (THR && s == NSTAGE - 1) apply_faults<R, E>(d, a.faults, fh, -1, b, j);
+                }
+                if constexpr (THR) {
+                    static_for<0, NB>([&](auto p) {
+                        constexpr int pp = p;
+                        thread_check<R, RAD, NB, pp>(d, vin, a, g, b, s);
+                    });
+                }
                 if constexpr (s < NSTAGE - 1) {
                     static_for<0, NB>([&](auto p) {
                         const int i = j + p * T;
@@ -521,8 +659,10 @@ pass_kernel(PassArgs a) {
                     d[m].im *= sc;
                 }
             }
-            if (fh >= 0) apply_faults<R, E>(d, a.faults, fh, -1, b, j);
-            if constexpr (FT) {
+            if constexpr (!THR) {
+                if (fh >= 0) apply_faults<R, E>(d, a.faults, fh, -1, b, j);
+            }
+            if constexpr (ENC) {
                 double Ar[3] = {0.0, 0.0, 0.0}, Ai[3] = {0.0, 0.0, 0.0};
                 cx<double> P = twA;
 #pragma unroll
@@ -544,11 +684,13 @@ pass_kernel(PassArgs a) {
                 const double sr = Ar[0] + kW3r * (Ar[1] + Ar[2]) - kW3i * (Ai[1] - Ai[2]);
                 const double si = Ai[0] + kW3r * (Ai[1] + Ai[2]) + kW3i * (Ar[1] - Ar[2]);
                 const double rr = sr * rotr - si * roti, ri = sr * roti + si * rotr;
-                const double w2 = double(b + 1);
                 D1r += rr;
                 D1i += ri;
-                D2r += w2 * rr;
-                D2i += w2 * ri;
+                if constexpr (BLK) {
+                    const double w2 = double(b + 1);
+                    D2r += w2 * rr;
+                    D2i += w2 * ri;
+                }
             }
             if constexpr (KIND == KIND_LAST) {
                 // transposed store: re-map through LDS so that lanes run along
@@ -571,7 +713,50 @@ pass_kernel(PassArgs a) {
             }
         }  // rounds
 
-        if constexpr (FT) {
+        if constexpr (SIG) {
+            // one residual per signal: sum over the T threads of signal c
+            double v[3] = {D1r, D1i, double(Ssum)};
+            if constexpr (T <= 64) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) v[q] = wave_sum(v[q], T);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) v[q] = wave_sum_dpp(v[q], Dpp64{});
+                if ((tid & 63) == 63) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) red[tid >> 6][q] = v[q];
+                }
+                __syncthreads();
+                if (j == 0) {
+                    v[0] = v[1] = v[2] = 0.0;
+                    for (int w = c * (T / 64); w < (c + 1) * (T / 64); ++w)
+                        for (int q = 0; q < 3; ++q) v[q] += red[w][q];
+                }
+            }
+            if (j == 0 && gsig < a.n_groups) {
+                const double tau = a.tau_coef * sqrt(v[2]);
+                if (!(sqrt(v[0] * v[0] + v[1] * v[1]) <= tau)) {
+                    const unsigned long long slot = atomicAdd(&a.rep->n_flag, 1ULL);
+                    if ((int64_t)slot < a.rec_cap) {
+                        DevRecord rc;
+                        rc.group = gsig;
+                        rc.pass = a.pass;
+                        rc.action = 1;  // detected
+                        rc.member = 0;  // the signal itself
+                        rc.method = 1;
+                        rc.d1r = v[0];
+                        rc.d1i = v[1];
+                        rc.d2r = v[0];  // one weight: the quotient is 1
+                        rc.d2i = v[1];
+                        rc.tau = tau;
+                        rc.s = v[2];
+                        a.recs[slot] = rc;
+                    }
+                }
+            }
+            if constexpr (T > 64) __syncthreads();
+        }
+        if constexpr (BLK) {
             double v[5] = {D1r, D1i, D2r, D2i, 0.0};
             if constexpr (NT % 64 == 0) {
 #pragma unroll
@@ -845,7 +1030,7 @@ __global__ void reset_kernel(DevReport *rep) {
 }
 
 // ------------------------------------------------------------- dispatch
-template <typename R, int M, int KIND, bool FT>
+template <typename R, int M, int KIND, int FT>
 static hipError_t launch_one(const PassArgs &a, int grid, hipStream_t st) {
     constexpr int NT = cfg_threads(sizeof(R) == 8, M, KIND);
     hipLaunchKernelGGL((pass_kernel<R, M, KIND, FT>), dim3(grid), dim3(NT), 0, st, a);
@@ -854,7 +1039,13 @@ static hipError_t launch_one(const PassArgs &a, int grid, hipStream_t st) {
 
 template <typename R, int M, int KIND>
 static hipError_t launch_kind(int ft, const PassArgs &a, int grid, hipStream_t st) {
-    return ft ? launch_one<R, M, KIND, true>(a, grid, st) : launch_one<R, M, KIND, false>(a, grid, st);
+    if (ft == FT_BLOCK) return launch_one<R, M, KIND, FT_BLOCK>(a, grid, st);
+    if (ft == FT_NONE) return launch_one<R, M, KIND, FT_NONE>(a, grid, st);
+    if constexpr (KIND == KIND_ROWS) {
+        if (ft == FT_SIGNAL) return launch_one<R, M, KIND, FT_SIGNAL>(a, grid, st);
+        if (ft == FT_THREAD) return launch_one<R, M, KIND, FT_THREAD>(a, grid, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename R, int M>
@@ -916,7 +1107,7 @@ hipError_t launch_correct(int fp64, int M, int kind, const PassArgs &a, int grid
     return by_m<float>(M, [&](auto m) { return correct_m<float, decltype(m)::value>(kind, a, grid, st); });
 }
 
-template <typename R, int M, int KIND, bool FT>
+template <typename R, int M, int KIND, int FT>
 static int occ_one() {
     int n = 0;
     constexpr int NT = cfg_threads(sizeof(R) == 8, M, KIND);
@@ -926,10 +1117,11 @@ static int occ_one() {
 
 template <typename R, int M>
 static int occ_m(int kind, int ft) {
-    if (kind == KIND_ROWS) return ft ? occ_one<R, M, KIND_ROWS, true>() : occ_one<R, M, KIND_ROWS, false>();
+    if (kind == KIND_ROWS) return ft ? occ_one<R, M, KIND_ROWS, FT_BLOCK>() : occ_one<R, M, KIND_ROWS, FT_NONE>();
     if constexpr (M >= 16 && M <= 1024) {
-        if (kind == KIND_STRIDED) return ft ? occ_one<R, M, KIND_STRIDED, true>() : occ_one<R, M, KIND_STRIDED, false>();
-        if (kind == KIND_LAST) return ft ? occ_one<R, M, KIND_LAST, true>() : occ_one<R, M, KIND_LAST, false>();
+        if (kind == KIND_STRIDED)
+            return ft ? occ_one<R, M, KIND_STRIDED, FT_BLOCK>() : occ_one<R, M, KIND_STRIDED, FT_NONE>();
+        if (kind == KIND_LAST) return ft ? occ_one<R, M, KIND_LAST, FT_BLOCK>() : occ_one<R, M, KIND_LAST, FT_NONE>();
     }
     return 0;
 }

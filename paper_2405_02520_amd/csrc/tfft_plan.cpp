@@ -81,6 +81,7 @@ struct tfft_plan_s {
     int dtype = 0;
     uint32_t flags = 0;
     double kappa = 16.0;
+    int scheme = TFFT_SCHEME_BLOCK;
     int passes = 0;
     int lens[kMaxPasses] = {0, 0, 0};
     PassPlan pass[kMaxPasses];
@@ -157,13 +158,23 @@ int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser, int grid_sca
     P.C = cfg_C(fp64, M, kind);
     P.stages = n_stages(M, P.E);
     const int G0 = Guser > 0 ? Guser : (kind == KIND_ROWS ? default_group(M) : 64);
-    if (kind == KIND_ROWS) {
+    int64_t tiles;  // workgroup iterations of the pass
+    if (kind == KIND_ROWS && p->scheme == TFFT_SCHEME_SIGNAL) {
+        // one-sided: every signal is a group of its own; tiles of C signals
+        P.G = 1;
+        P.rb = 1;
+        P.n_strips = 1;
+        P.n_outer = p->batch;
+        P.n_groups = p->batch;
+        tiles = (p->batch + P.C - 1) / P.C;
+    } else if (kind == KIND_ROWS) {
         if (G0 % P.C != 0) return TFFT_E_UNSUPPORTED;
         P.G = G0;
         P.rb = 1;
         P.n_strips = 1;
         P.n_outer = p->batch;
         P.n_groups = (p->batch + P.G - 1) / P.G;
+        tiles = P.n_groups;
     } else {
         int64_t n_sub;  // sub-signals per outer unit
         if (kind == KIND_STRIDED) {
@@ -186,6 +197,7 @@ int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser, int grid_sca
         P.G = P.C * P.rb;
         P.n_strips = n_sub / P.C;
         P.n_groups = P.n_strips * ((P.n_outer + P.rb - 1) / P.rb);
+        tiles = P.n_groups;
     }
     int64_t cap = std::max<int64_t>(8, (int64_t)TFFT_GRID_THREADS / cfg_threads(fp64, M, kind));
     if (TFFT_GRID_MULT > 0) {
@@ -197,7 +209,7 @@ int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser, int grid_sca
     }
     if (grid_scale > 0) cap <<= grid_scale;
     if (grid_scale < 0) cap = std::max<int64_t>(8, cap >> (-grid_scale));
-    int64_t grid = std::min<int64_t>(P.n_groups, cap);
+    int64_t grid = std::min<int64_t>(tiles, cap);
     if (grid >= 8) grid = (grid + 7) / 8 * 8;
     P.grid = (int)std::max<int64_t>(1, grid);
     const double u = fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
@@ -342,9 +354,14 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
         A.rec_cap = p->rec_cap;
         A.fault_head = P.d_fault_head;
         A.faults = P.d_faults;
-        if (launch_pass(fp64, P.M, P.kind, ft, A, P.grid, st) != hipSuccess) return TFFT_E_HIP;
+        A.kappa_u = p->kappa * (fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
+        A.fix = mode == TFFT_FT_CORRECT;
+        const int scheme_ft = !ft ? FT_NONE
+                                  : (p->scheme == TFFT_SCHEME_SIGNAL ? FT_SIGNAL
+                                                                     : (p->scheme == TFFT_SCHEME_THREAD ? FT_THREAD : FT_BLOCK));
+        if (launch_pass(fp64, P.M, P.kind, scheme_ft, A, P.grid, st) != hipSuccess) return TFFT_E_HIP;
         if (timed && hipEventRecord(p->ev[1 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
-        if (mode == TFFT_FT_CORRECT) {
+        if (mode == TFFT_FT_CORRECT && p->scheme != TFFT_SCHEME_THREAD) {
             // one workgroup per possible record, at most 1024; a workgroup
             // with no record of this pass exits at once
             const int cgrid = (int)std::min<int64_t>(1024, std::max<int64_t>(1, P.n_groups));
@@ -353,7 +370,7 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
         if (timed && hipEventRecord(p->ev[2 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
     }
     p->timed_last = timed ? 1 : 0;
-    p->launched_correct = mode == TFFT_FT_CORRECT;
+    p->launched_correct = mode == TFFT_FT_CORRECT && p->scheme != TFFT_SCHEME_THREAD;
     p->last_stream = st;
     p->executed = 1;
     p->last_mode = mode;
@@ -401,7 +418,12 @@ int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_
     if (flags & ~(uint32_t)TFFT_INVERSE_UNSCALED) return TFFT_E_INVALID;
     const int force_passes = opt ? opt->passes : 0;
     const int grid_scale = opt ? opt->grid_scale : 0;
+    const int scheme = opt ? opt->scheme : TFFT_SCHEME_BLOCK;
     if (force_passes < 0 || force_passes > 3 || grid_scale < -3 || grid_scale > 3) return TFFT_E_INVALID;
+    if (scheme < TFFT_SCHEME_BLOCK || scheme > TFFT_SCHEME_THREAD) return TFFT_E_INVALID;
+    // the one-sided and thread-level schemes exist for single-pass plans
+    if (scheme != TFFT_SCHEME_BLOCK && (ilog2_64(n) > 12 || force_passes > 1)) return TFFT_E_UNSUPPORTED;
+    if (scheme != TFFT_SCHEME_BLOCK && host_off) return TFFT_E_UNSUPPORTED;
     {
         const int kk = ilog2_64(n);
         if ((force_passes == 1 && kk > 12) || (force_passes == 2 && (kk < 8 || kk > 20)) ||
@@ -417,6 +439,7 @@ int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_
     p->dtype = dtype;
     p->flags = flags;
     p->kappa = (opt && opt->kappa > 0) ? opt->kappa : 16.0;
+    p->scheme = scheme;
     p->extent = host_off ? extent : n * batch;
     const int k = ilog2_64(n);
     int rc = TFFT_OK;
@@ -551,7 +574,7 @@ int tfft_get_report(tfft_plan p, tfft_counts *counts, tfft_record *recs, int64_t
         const int mem = d.member >= 0 ? d.member : 0;
         if (P.kind == KIND_ROWS) {
             r.signal = d.group * P.G + mem;
-            r.sub = 0;
+            r.sub = d.method == TFFT_LOC_THREAD ? (int64_t)d.s : 0;
         } else {
             const int64_t strip = d.group % P.n_strips, ublk = d.group / P.n_strips;
             const int64_t u = ublk * P.rb + mem / P.C, i = strip * P.C + mem % P.C;
@@ -709,6 +732,11 @@ struct tfft_ragged_s {
     hipStream_t g_stream = nullptr;
     hipStream_t last_stream = nullptr;
     int executed = 0, last_mode = 0;
+    // parallel branches of the captured graph: classes are independent, so
+    // they are captured on TFFT_GRAPH_BRANCHES forked streams and joined
+    hipStream_t aux[TFFT_GRAPH_BRANCHES] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[TFFT_GRAPH_BRANCHES] = {};
+    std::vector<int> branch_of;  // class -> branch
 };
 
 namespace {
@@ -741,6 +769,52 @@ int ragged_launch(tfft_ragged_s *r, const void *d_in, void *d_out, int ft_mode, 
         if (rc != TFFT_OK) return rc;
     }
     return TFFT_OK;
+}
+
+// Balance the classes over the branches by bytes (largest first, each to the
+// least loaded branch).
+void assign_branches(tfft_ragged_s *r) {
+    const size_t nc = r->classes.size();
+    std::vector<size_t> order(nc);
+    for (size_t c = 0; c < nc; ++c) order[c] = c;
+    auto bytes = [&](size_t c) { return r->classes[c].n * (int64_t)r->classes[c].members.size(); };
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return bytes(a) > bytes(b); });
+    int64_t load[TFFT_GRAPH_BRANCHES] = {};
+    r->branch_of.assign(nc, 0);
+    for (size_t c : order) {
+        int b = 0;
+        for (int q = 1; q < TFFT_GRAPH_BRANCHES; ++q)
+            if (load[q] < load[b]) b = q;
+        r->branch_of[c] = b;
+        load[b] += bytes(c);
+    }
+}
+
+// Launch every class on its branch, forked from and joined back into st
+// (used under stream capture, where it records a graph with parallel
+// branches).
+int ragged_launch_branches(tfft_ragged_s *r, const void *d_in, void *d_out, int ft_mode, int inverse,
+                           hipStream_t st) {
+    if (!r->ev_fork) {
+        if (hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming) != hipSuccess) return TFFT_E_HIP;
+        for (int b = 0; b < TFFT_GRAPH_BRANCHES; ++b)
+            if (hipStreamCreateWithFlags(&r->aux[b], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&r->ev_join[b], hipEventDisableTiming) != hipSuccess)
+                return TFFT_E_HIP;
+        assign_branches(r);
+    }
+    const int nb = (int)std::min<size_t>(TFFT_GRAPH_BRANCHES, r->classes.size());
+    if (hipEventRecord(r->ev_fork, st) != hipSuccess) return TFFT_E_HIP;
+    for (int b = 0; b < nb; ++b)
+        if (hipStreamWaitEvent(r->aux[b], r->ev_fork, 0) != hipSuccess) return TFFT_E_HIP;
+    int rc = TFFT_OK;
+    for (size_t c = 0; c < r->classes.size() && rc == TFFT_OK; ++c)
+        rc = exec(r->classes[c].plan, d_in, d_out, ft_mode, r->aux[r->branch_of[c] % nb], inverse != 0);
+    // join every forked branch, also after a failure, so that the capture ends cleanly
+    for (int b = 0; b < nb; ++b)
+        if (hipEventRecord(r->ev_join[b], r->aux[b]) != hipSuccess || hipStreamWaitEvent(st, r->ev_join[b], 0) != hipSuccess)
+            rc = TFFT_E_HIP;
+    return rc;
 }
 
 }  // namespace
@@ -802,6 +876,11 @@ int tfft_ragged_destroy(tfft_ragged r) {
     Guard guard(r->device);
     drop_graph(r);
     for (auto &C : r->classes) tfft_plan_destroy(C.plan);
+    for (int b = 0; b < TFFT_GRAPH_BRANCHES; ++b) {
+        if (r->aux[b]) (void)hipStreamDestroy(r->aux[b]);
+        if (r->ev_join[b]) (void)hipEventDestroy(r->ev_join[b]);
+    }
+    if (r->ev_fork) (void)hipEventDestroy(r->ev_fork);
     delete r;
     return TFFT_OK;
 }
@@ -821,7 +900,7 @@ int tfft_ragged_exec(tfft_ragged r, const void *d_in, void *d_out, int ft_mode, 
             drop_graph(r);
             for (auto &C : r->classes) C.plan->timing = 0;  // no event nodes in the graph
             if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return TFFT_E_HIP;
-            rc = ragged_launch(r, d_in, d_out, ft_mode, inverse, st);
+            rc = ragged_launch_branches(r, d_in, d_out, ft_mode, inverse, st);
             hipGraph_t g = nullptr;
             const hipError_t e = hipStreamEndCapture(st, &g);
             if (rc != TFFT_OK || e != hipSuccess) {

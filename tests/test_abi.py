@@ -85,7 +85,7 @@ def test_record_layouts_match_header(tf):
 
 
 def test_options_layout_and_pass_forcing(tf):
-    assert ctypes.sizeof(tf.tfft_options) == 4 + 4 + 8 + 4 + 4 + 6 * 4
+    assert ctypes.sizeof(tf.tfft_options) == 4 + 4 + 8 + 4 + 4 + 4 + 5 * 4
     h = ctypes.c_void_p()
     for passes, grid_scale in [(4, 0), (-1, 0), (0, 4), (0, -4)]:
         opt = tf.tfft_options(passes=passes, grid_scale=grid_scale)
@@ -129,3 +129,15 @@ def test_null_ragged_is_rejected(tf):
     assert tf.tfft_ragged_tune(None, 16, 16, None, 1) == tf.E_INVALID
     assert tf.tfft_ragged_info(None, None, None, None, None, 0) == tf.E_INVALID
     assert tf.tfft_ragged_create(None, 1, None, None, 0, None) == tf.E_INVALID
+
+
+def test_scheme_option_validation(tf):
+    h = ctypes.c_void_p()
+    for scheme in (-1, 3):
+        opt = tf.tfft_options(scheme=scheme)
+        assert tf.tfft_plan_create_with(ctypes.byref(h), 1024, 4, 0, ctypes.byref(opt)) == tf.E_INVALID
+    # the one-sided and thread-level schemes are single-pass only
+    for scheme in (tf.SCHEME_SIGNAL, tf.SCHEME_THREAD):
+        opt = tf.tfft_options(scheme=scheme)
+        assert tf.tfft_plan_create_with(ctypes.byref(h), 1 << 13, 4, 0, ctypes.byref(opt)) == tf.E_UNSUPPORTED
+    assert not h.value
