@@ -536,6 +536,22 @@ def main():
             }
         torch.cuda.synchronize()
 
+    # what a plain device-to-device copy of the same bytes achieves (the
+    # practical HBM ceiling next to the 8 TB/s peak)
+    src = xin[dtypes[0]].view(torch.uint8)
+    dst = ybuf[: src.numel()]
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(5):
+            dst.copy_(src)
+        ev1.record(stream)
+    ev1.synchronize()
+    copy_gbps = 2 * src.numel() * 5 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    roofline["copy_GBps"] = round(copy_gbps, 1)
+    roofline["frac_of_copy"] = round(achieved / copy_gbps, 4)
+
     res = {
         "metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",

@@ -29,9 +29,17 @@ constexpr int ipowc(int b, int e) { return e == 0 ? 1 : b * ipowc(b, e - 1); }
 #ifndef TFFT_E64
 #define TFFT_E64 8
 #endif
-// Elements held by one thread (the thread-level radix, Section IV-A.2).
+// Elements held by one thread (the thread-level radix, Section IV-A.2);
+// complex128 transforms of at least TFFT_E64_BIG_MIN points may use a larger
+// thread radix (fewer stages and threads per signal).
+#ifndef TFFT_E64_BIG
+#define TFFT_E64_BIG TFFT_E64
+#endif
+#ifndef TFFT_E64_BIG_MIN
+#define TFFT_E64_BIG_MIN 4096
+#endif
 constexpr int cfg_E(int fp64, int M) {
-    const int e = fp64 ? TFFT_E64 : TFFT_E32;
+    const int e = fp64 ? (M >= TFFT_E64_BIG_MIN ? TFFT_E64_BIG : TFFT_E64) : TFFT_E32;
     return M >= e ? e : M;
 }
 // Threads of a multi-pass tile (a 512-thread workgroup caps a wavefront at
@@ -104,6 +112,31 @@ constexpr int cfg_twreg(int fp64, int M, int kind) { return fp64 ? TFFT_TWREG64 
 constexpr int cfg_creg(int fp64, int M, int kind) { return fp64 ? TFFT_CREG64 : TFFT_CREG32; }
 // Issue the next tile's loads before transforming the current one.
 constexpr int cfg_prefetch(int fp64, int M, int kind) { return fp64 ? TFFT_PREFETCH64 : TFFT_PREFETCH32; }
+// Order the register prefetch after the current tile's values are in
+// registers, with branch-free tile loads (see the pass kernel): multi-pass
+// tiles, and one-pass tiles of at least TFFT_PF_FENCE_ROWS_MIN points
+// (measured: faster there, slower for the short one-pass sizes).
+#ifndef TFFT_PF_FENCE
+#define TFFT_PF_FENCE 1
+#endif
+#ifndef TFFT_PF_FENCE_ROWS_MIN
+#define TFFT_PF_FENCE_ROWS_MIN 4096
+#endif
+constexpr int cfg_pf_fence(int fp64, int M, int kind) {
+    return TFFT_PF_FENCE && (kind != KIND_ROWS || M >= TFFT_PF_FENCE_ROWS_MIN) ? 1 : 0;
+}
+// Prefetch of the next tile straight into a second LDS buffer
+// (global_load_lds_dwordx4: 16-byte elements, i.e. complex128) for one-pass
+// tiles that hold one signal (C = 1) whose two buffers fit in 128 KiB.
+#ifndef TFFT_LDSPF64
+#define TFFT_LDSPF64 1
+#endif
+constexpr int cfg_ldspf(int fp64, int M, int kind) {
+    return (fp64 && TFFT_LDSPF64 && kind == KIND_ROWS && cfg_C(fp64, M, kind) == 1 && M * 16 * 2 <= 131072 &&
+            (M / cfg_E(fp64, M)) % 64 == 0)
+               ? 1
+               : 0;
+}
 constexpr int cfg_threads(int fp64, int M, int kind) { return cfg_C(fp64, M, kind) * (M / cfg_E(fp64, M)); }
 
 // Radix sequence: as many stages of radix E as fit, then one stage of the

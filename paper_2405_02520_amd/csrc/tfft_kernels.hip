@@ -288,6 +288,7 @@ __device__ __forceinline__ void apply_faults(cx<R> (&d)[E], const DevFault *F, i
 }
 
 constexpr double kW3r = -0.5;
+__device__ const int32_t kNoFault = -1;
 constexpr double kW3i = -0.86602540378443864676;  // w_3 = exp(-2 pi i / 3)
 
 __device__ __forceinline__ double wave_sum(double v, int width) {
@@ -446,6 +447,7 @@ __global__ void __launch_bounds__(cfg_threads(sizeof(R) == 8, M, KIND))
 pass_kernel(PassArgs a) {
     constexpr int FP64 = sizeof(R) == 8;
     constexpr bool BLK = FT == FT_BLOCK, SIG = FT == FT_SIGNAL, THR = FT == FT_THREAD;
+    constexpr bool PF_FENCE = cfg_pf_fence(FP64, M, KIND) != 0;
     constexpr bool ENC = BLK || SIG;  // input and output encodings
     constexpr int E = cfg_E(FP64, M);
     constexpr int T = M / E;
@@ -480,11 +482,34 @@ pass_kernel(PassArgs a) {
     constexpr bool CREG = ENC && cfg_creg(FP64, M, KIND) != 0;
     const cx<R> *stw = reinterpret_cast<const cx<R> *>(a.stw);
     const cx<double> *cv = reinterpret_cast<const cx<double> *>(a.cvec);
+    // With the LDS prefetch, stage twiddles come from an LDS copy of the
+    // first octant, w_M^t for t <= M/8, and the exact symmetries of the
+    // table (the host builds it from the same octant): no global load in the
+    // transform, whose wait would also wait for the prefetch.
+    constexpr bool TWLDS = cfg_ldspf(FP64, M, KIND) != 0 && M >= 8;
+    __shared__ cx<R> twl[TWLDS ? M / 8 + 1 : 1];
+    if constexpr (TWLDS) {
+        for (int t = tid; t <= M / 8; t += NT) twl[t] = ldg(stw + t);
+        __syncthreads();
+    }
+    auto tw_oct = [&](int t) -> cx<R> {
+        constexpr int M4 = M / 4, M8 = M / 8;
+        const int qd = t / M4, r = t % M4;
+        const cx<R> v = twl[r <= M8 ? r : M4 - r];
+        // w^r for r > M/8 is (-Im, -Re) of w^(M/4 - r)
+        const R a = r <= M8 ? v.re : -v.im, b = r <= M8 ? v.im : -v.re;
+        // times (-i)^qd
+        const R re = qd == 0 ? a : (qd == 1 ? b : (qd == 2 ? -a : -b));
+        const R im = qd == 0 ? b : (qd == 1 ? -a : (qd == 2 ? -b : a));
+        return cx<R>{re, im};
+    };
     auto stage_tw = [&](auto S, auto p, auto q) -> cx<R> {
         constexpr int s = S;
         constexpr int RAD = St::radix(s), NS = St::ns(s);
         const int i = j + p * T;
-        return ldg(stw + ((i % NS) * q) * (M / (NS * RAD)));
+        const int t = ((i % NS) * q) * (M / (NS * RAD));
+        if constexpr (TWLDS) return tw_oct(t);
+        else return ldg(stw + t);
     };
     cx<R> tw[TWREG ? St::tw_count() : 1];
     if constexpr (TWREG) {
@@ -521,9 +546,20 @@ pass_kernel(PassArgs a) {
     // this workgroup's next group) are issued before the current tile is
     // transformed, so every wavefront keeps two tiles of HBM reads in flight.
     cx<R> nx[E];
+    bool nx_ok = false;
     auto load_tile = [&](int64_t gg, int rr) {
         const MemberLoc Ln = mloc(gg, rr);
-        if (gg < n_iter && Ln.valid) {
+        nx_ok = gg < n_iter && Ln.valid;
+        if constexpr (PF_FENCE) {
+            // branch-free: a missing member re-reads element 0 and is zeroed
+            // when consumed, so the compiler's count of outstanding loads
+            // stays exact across the loop (no join of two load states)
+            const cx<R> *s = in + (nx_ok ? Ln.in_off : 0);
+            const uint32_t st = nx_ok ? Ln.in_stride : 0u;
+            const uint32_t j0 = nx_ok ? (uint32_t)j : 0u;
+#pragma unroll
+            for (int m = 0; m < E; ++m) nx[m] = ld_stream(s + (j0 + (uint32_t)(T * m)) * st);
+        } else if (nx_ok) {
             const cx<R> *s = in + Ln.in_off;
 #pragma unroll
             for (int m = 0; m < E; ++m) nx[m] = ld_stream(s + (uint32_t)(j + T * m) * Ln.in_stride);
@@ -532,13 +568,41 @@ pass_kernel(PassArgs a) {
             for (int m = 0; m < E; ++m) nx[m] = cx<R>{R(0), R(0)};
         }
     };
-    constexpr bool PREFETCH = cfg_prefetch(FP64, M, KIND) != 0;
+    // Asynchronous prefetch into LDS: the next tile's elements go straight
+    // from HBM into a second LDS buffer (global_load_lds_dwordx4, no VGPRs
+    // held) while the current tile is transformed.  Element q = tid + NT m of
+    // a tile is member q / M, position q % M, so each wavefront's 64 lanes
+    // fill 64 consecutive LDS slots (the instruction's layout).
+    constexpr bool LDSPF = cfg_ldspf(FP64, M, KIND) != 0;
+    constexpr bool PREFETCH = !LDSPF && cfg_prefetch(FP64, M, KIND) != 0;
+    __shared__ cx<R> nbuf[LDSPF ? C * M : 1];
+    auto dma_tile = [&](int64_t gg, int rr) {
+        if constexpr (LDSPF) {
+            static_assert(C == 1 && NT % 64 == 0 && sizeof(cx<R>) == 16,
+                          "LDS prefetch: one 16-byte-element signal per tile, full waves");
+            // one signal per tile: a workgroup-uniform base, lane offsets q
+            MemberLoc Lq;
+            if constexpr (SIG) Lq = member_loc<M, KIND, C>(a, gg, 0);
+            else Lq = member_loc<M, KIND, C>(a, gg, rr);
+            if (gg < n_iter && Lq.valid) {
+                const cx<R> *src = in + Lq.in_off;
+#pragma unroll
+                for (int m = 0; m < E; ++m)
+                    __builtin_amdgcn_global_load_lds((const void *)(src + tid + NT * m),
+                                                     (__attribute__((address_space(3))) void *)(nbuf + (tid & ~63) + NT * m),
+                                                     16, 0, 0);
+            }
+        }
+    };
     if constexpr (PREFETCH) load_tile(wl, 0);
+    if constexpr (LDSPF) dma_tile(wl, 0);
     for (int64_t g = wl; g < n_iter; g += nwg) {
         const int64_t gsig = g * C + c;  // FT_SIGNAL: this thread's signal (= its group)
-        int fh;
-        if constexpr (SIG) fh = (a.fault_head && gsig < a.n_groups) ? a.fault_head[gsig] : -1;
-        else fh = a.fault_head ? a.fault_head[g] : -1;
+        // the fault lookup reads a table entry or a constant -1 (no branch)
+        const int32_t *fhp;
+        if constexpr (SIG) fhp = (a.fault_head && gsig < a.n_groups) ? a.fault_head + gsig : &kNoFault;
+        else fhp = a.fault_head ? a.fault_head + g : &kNoFault;
+        const int fh = *fhp;
         double D1r = 0.0, D1i = 0.0, D2r = 0.0, D2i = 0.0;
         R Ssum = R(0);  // energy of the group's inputs, for the threshold only
         for (int r = 0; r < rounds; ++r) {
@@ -548,15 +612,33 @@ pass_kernel(PassArgs a) {
             cx<R> *dst = out + L.out_off;
             const uint32_t ostr = (uint32_t)L.out_stride;
             cx<R> d[E];
-            if constexpr (PREFETCH) {
+            if constexpr (LDSPF) {
+                // this tile's DMA (issued one iteration earlier) has landed
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
 #pragma unroll
-                for (int m = 0; m < E; ++m) d[m] = nx[m];
+                for (int m = 0; m < E; ++m) d[m] = L.valid ? nbuf[c * M + j + T * m] : cx<R>{R(0), R(0)};
+                __syncthreads();  // every read of nbuf precedes the next DMA into it
+                // (the next DMA is issued after the input encoding below, so
+                // that the checksum vector's loads do not wait for it)
+            } else if constexpr (PREFETCH) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) d[m] = (!PF_FENCE || nx_ok) ? nx[m] : cx<R>{R(0), R(0)};
+                if constexpr (PF_FENCE) {
+                    // Materialise this tile's values before the next tile's
+                    // loads are issued: the vector-memory counter cannot tell
+                    // the two apart, so a load hoisted above this point would
+                    // make the wait for this tile also wait for the next one.
+#pragma unroll
+                    for (int m = 0; m < E; ++m) asm volatile("" : "+v"(d[m].re), "+v"(d[m].im));
+                    asm volatile("" ::: "memory");
+                }
                 if (r + 1 < rounds) load_tile(g, r + 1);
                 else load_tile(g + nwg, 0);
             } else {
                 load_tile(g, r);
 #pragma unroll
-                for (int m = 0; m < E; ++m) d[m] = nx[m];
+                for (int m = 0; m < E; ++m) d[m] = (!PF_FENCE || nx_ok) ? nx[m] : cx<R>{R(0), R(0)};
             }
             if constexpr (ENC) {
                 double lr = 0.0, li = 0.0;
@@ -577,6 +659,12 @@ pass_kernel(PassArgs a) {
                     D2r -= w2 * lr;
                     D2i -= w2 * li;
                 }
+                if constexpr (LDSPF) asm volatile("" : "+v"(D1r), "+v"(D1i), "+v"(Ssum));
+            }
+            if constexpr (LDSPF) {
+                asm volatile("" ::: "memory");
+                if (r + 1 < rounds) dma_tile(g, r + 1);
+                else dma_tile(g + nwg, 0);
             }
             if (a.conj_in) {
 #pragma unroll
