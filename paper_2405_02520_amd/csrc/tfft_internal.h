@@ -38,8 +38,18 @@ constexpr int ipowc(int b, int e) { return e == 0 ? 1 : b * ipowc(b, e - 1); }
 #ifndef TFFT_E64_BIG_MIN
 #define TFFT_E64_BIG_MIN 4096
 #endif
-constexpr int cfg_E(int fp64, int M) {
-    const int e = fp64 ? (M >= TFFT_E64_BIG_MIN ? TFFT_E64_BIG : TFFT_E64) : TFFT_E32;
+// complex64 strided / last passes of at least TFFT_E32_MP_BIG_MIN points may
+// use a larger thread radix, so that their tiles keep >= 16 columns (128-byte
+// rows) within 512 threads.
+#ifndef TFFT_E32_MP_BIG
+#define TFFT_E32_MP_BIG TFFT_E32
+#endif
+#ifndef TFFT_E32_MP_BIG_MIN
+#define TFFT_E32_MP_BIG_MIN 512
+#endif
+constexpr int cfg_E(int fp64, int M, int kind) {
+    const int e = fp64 ? (M >= TFFT_E64_BIG_MIN ? TFFT_E64_BIG : TFFT_E64)
+                       : ((kind != KIND_ROWS && M >= TFFT_E32_MP_BIG_MIN) ? TFFT_E32_MP_BIG : TFFT_E32);
     return M >= e ? e : M;
 }
 // Threads of a multi-pass tile (a 512-thread workgroup caps a wavefront at
@@ -56,7 +66,7 @@ constexpr int cfg_E(int fp64, int M) {
 // of LDS allow (at most 32 signals), because the strided loads and the
 // transposed stores of those passes move C adjacent elements per row.
 constexpr int cfg_C(int fp64, int M, int kind) {
-    const int E = cfg_E(fp64, M);
+    const int E = cfg_E(fp64, M, kind);
     const int T = M / E;
     const int S = fp64 ? 16 : 8;
     int c = kind == KIND_ROWS ? 256 / (T > 0 ? T : 1) : 32;
@@ -125,19 +135,22 @@ constexpr int cfg_prefetch(int fp64, int M, int kind) { return fp64 ? TFFT_PREFE
 constexpr int cfg_pf_fence(int fp64, int M, int kind) {
     return TFFT_PF_FENCE && (kind != KIND_ROWS || M >= TFFT_PF_FENCE_ROWS_MIN) ? 1 : 0;
 }
+constexpr int cfg_threads(int fp64, int M, int kind) { return cfg_C(fp64, M, kind) * (M / cfg_E(fp64, M, kind)); }
 // Prefetch of the next tile straight into a second LDS buffer
-// (global_load_lds_dwordx4: 16-byte elements, i.e. complex128) for one-pass
-// tiles that hold one signal (C = 1) whose two buffers fit in 128 KiB.
+// (global_load_lds_dwordx4: 16-byte elements, i.e. complex128): strided
+// tiles, and row tiles whose members span whole wavefronts (T % 64 == 0),
+// when both buffers fit in 128 KiB.  TFFT_LDSPF64: 0 off, 1 one-pass tiles
+// only, 2 all kinds.
 #ifndef TFFT_LDSPF64
-#define TFFT_LDSPF64 1
+#define TFFT_LDSPF64 2
 #endif
 constexpr int cfg_ldspf(int fp64, int M, int kind) {
-    return (fp64 && TFFT_LDSPF64 && kind == KIND_ROWS && cfg_C(fp64, M, kind) == 1 && M * 16 * 2 <= 131072 &&
-            (M / cfg_E(fp64, M)) % 64 == 0)
+    return (fp64 && (TFFT_LDSPF64 == 2 || (TFFT_LDSPF64 == 1 && kind == KIND_ROWS)) &&
+            (kind == KIND_STRIDED || (M / cfg_E(fp64, M, kind)) % 64 == 0) &&
+            cfg_C(fp64, M, kind) * M * 16 * 2 <= 131072 && cfg_threads(fp64, M, kind) % 64 == 0)
                ? 1
                : 0;
 }
-constexpr int cfg_threads(int fp64, int M, int kind) { return cfg_C(fp64, M, kind) * (M / cfg_E(fp64, M)); }
 
 // Radix sequence: as many stages of radix E as fit, then one stage of the
 // remaining factor (which divides E).

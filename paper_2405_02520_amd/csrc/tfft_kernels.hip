@@ -449,7 +449,7 @@ pass_kernel(PassArgs a) {
     constexpr bool BLK = FT == FT_BLOCK, SIG = FT == FT_SIGNAL, THR = FT == FT_THREAD;
     constexpr bool PF_FENCE = cfg_pf_fence(FP64, M, KIND) != 0;
     constexpr bool ENC = BLK || SIG;  // input and output encodings
-    constexpr int E = cfg_E(FP64, M);
+    constexpr int E = cfg_E(FP64, M, KIND);
     constexpr int T = M / E;
     constexpr int C = cfg_C(FP64, M, KIND);
     constexpr int NT = C * T;
@@ -570,27 +570,33 @@ pass_kernel(PassArgs a) {
     };
     // Asynchronous prefetch into LDS: the next tile's elements go straight
     // from HBM into a second LDS buffer (global_load_lds_dwordx4, no VGPRs
-    // held) while the current tile is transformed.  Element q = tid + NT m of
-    // a tile is member q / M, position q % M, so each wavefront's 64 lanes
-    // fill 64 consecutive LDS slots (the instruction's layout).
+    // held) while the current tile is transformed.  Every thread prefetches
+    // its own E elements of its own member; the instruction writes lane l of
+    // a wavefront to slot base + l, so the slots of a thread's element m are
+    // (strided tiles, [pos][slot]) tid + NT m, or (row tiles, [slot][pos],
+    // T a multiple of 64 so a wavefront stays inside one member)
+    // c M + j + T m.  A thread reads back only what its own lane wrote.
     constexpr bool LDSPF = cfg_ldspf(FP64, M, KIND) != 0;
     constexpr bool PREFETCH = !LDSPF && cfg_prefetch(FP64, M, KIND) != 0;
     __shared__ cx<R> nbuf[LDSPF ? C * M : 1];
+    auto nslot = [&](int m) -> int {
+        if constexpr (KIND == KIND_STRIDED) return tid + NT * m;
+        else return c * M + j + T * m;
+    };
     auto dma_tile = [&](int64_t gg, int rr) {
         if constexpr (LDSPF) {
-            static_assert(C == 1 && NT % 64 == 0 && sizeof(cx<R>) == 16,
-                          "LDS prefetch: one 16-byte-element signal per tile, full waves");
-            // one signal per tile: a workgroup-uniform base, lane offsets q
-            MemberLoc Lq;
-            if constexpr (SIG) Lq = member_loc<M, KIND, C>(a, gg, 0);
-            else Lq = member_loc<M, KIND, C>(a, gg, rr);
-            if (gg < n_iter && Lq.valid) {
-                const cx<R> *src = in + Lq.in_off;
+            static_assert(NT % 64 == 0 && sizeof(cx<R>) == 16 && (KIND == KIND_STRIDED || T % 64 == 0),
+                          "LDS prefetch: 16-byte elements, wavefronts inside one member");
+            const MemberLoc Ln = mloc(gg, rr);
+            if (gg < n_iter && Ln.valid) {
+                const cx<R> *src = in + Ln.in_off;
 #pragma unroll
-                for (int m = 0; m < E; ++m)
-                    __builtin_amdgcn_global_load_lds((const void *)(src + tid + NT * m),
-                                                     (__attribute__((address_space(3))) void *)(nbuf + (tid & ~63) + NT * m),
-                                                     16, 0, 0);
+                for (int m = 0; m < E; ++m) {
+                    const int base = nslot(m) - (tid & 63);  // wavefront-uniform
+                    __builtin_amdgcn_global_load_lds((const void *)(src + (uint32_t)(j + T * m) * Ln.in_stride),
+                                                     (__attribute__((address_space(3))) void *)(nbuf + base), 16,
+                                                     0, 0);
+                }
             }
         }
     };
@@ -612,13 +618,21 @@ pass_kernel(PassArgs a) {
             cx<R> *dst = out + L.out_off;
             const uint32_t ostr = (uint32_t)L.out_stride;
             cx<R> d[E];
+            // inter-pass twiddle of this member (strided passes), loaded
+            // before any prefetch is issued so that waiting for it never
+            // waits for the prefetch
+            cx<double> twA{1.0, 0.0}, twB{1.0, 0.0};
+            if constexpr (KIND == KIND_STRIDED) {
+                // w_L^{k i} = w_N^{k i N/L}
+                twA = itw(a, (int64_t(j) * L.tw_i * a.tw_scale) % a.n);
+                twB = itw(a, (int64_t(T) * L.tw_i * a.tw_scale) % a.n);
+            }
             if constexpr (LDSPF) {
-                // this tile's DMA (issued one iteration earlier) has landed
+                // this tile's DMA (issued one iteration earlier) has landed;
+                // each thread reads only the slots its own lane filled
                 asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-                __syncthreads();
 #pragma unroll
-                for (int m = 0; m < E; ++m) d[m] = L.valid ? nbuf[c * M + j + T * m] : cx<R>{R(0), R(0)};
-                __syncthreads();  // every read of nbuf precedes the next DMA into it
+                for (int m = 0; m < E; ++m) d[m] = L.valid ? nbuf[nslot(m)] : cx<R>{R(0), R(0)};
                 // (the next DMA is issued after the input encoding below, so
                 // that the checksum vector's loads do not wait for it)
             } else if constexpr (PREFETCH) {
@@ -661,6 +675,8 @@ pass_kernel(PassArgs a) {
                 }
                 if constexpr (LDSPF) asm volatile("" : "+v"(D1r), "+v"(D1i), "+v"(Ssum));
             }
+            if constexpr (LDSPF && KIND == KIND_STRIDED)
+                asm volatile("" : "+v"(twA.re), "+v"(twA.im), "+v"(twB.re), "+v"(twB.im));
             if constexpr (LDSPF) {
                 asm volatile("" ::: "memory");
                 if (r + 1 < rounds) dma_tile(g, r + 1);
@@ -723,11 +739,7 @@ pass_kernel(PassArgs a) {
             // final values: register m holds output position k = j + T m
             // inter-pass twiddle (COLS): w_N^{k sub} = A B^m with A = w_N^{j sub},
             // B = w_N^{T sub}, products in fp64, each rounded once
-            cx<double> twA{1.0, 0.0}, twB{1.0, 0.0};
             if constexpr (KIND == KIND_STRIDED) {
-                // w_L^{k i} = w_N^{k i N/L}
-                twA = itw(a, (int64_t(j) * L.tw_i * a.tw_scale) % a.n);
-                twB = itw(a, (int64_t(T) * L.tw_i * a.tw_scale) % a.n);
                 cx<double> P = twA;
 #pragma unroll
                 for (int m = 0; m < E; ++m) {

@@ -154,7 +154,7 @@ int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser, int grid_sca
     const int fp64 = p->dtype == TFFT_C128;
     P.M = M;
     P.kind = kind;
-    P.E = cfg_E(fp64, M);
+    P.E = cfg_E(fp64, M, kind);
     P.C = cfg_C(fp64, M, kind);
     P.stages = n_stages(M, P.E);
     const int G0 = Guser > 0 ? Guser : (kind == KIND_ROWS ? default_group(M) : 64);
