@@ -48,9 +48,9 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="LOG2_BYTES",
                     help="only run a plain device-to-device copy of 2^LOG2_BYTES bytes (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
-    ap.add_argument("--summarize-pmc", nargs=3, metavar=("READS_DIR", "WRITE_DIR", "COPY_LOG2"),
-                    help="turn rocprofv3 --pmc output directories (TCC_EA0_RDREQ_{32B,64B,128B}_sum, WRITE_SIZE) "
-                         "of runs that included the copy calibration into profiles/pmc_traffic.json")
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="turn rocprofv3 --pmc output directories DIR/<label>_<FETCH_SIZE|WRITE_SIZE> (label: copy "
+                         "or <dtype>_k<k>) into profiles/pmc_traffic.json")
     ap.add_argument("--workload", default="sweep", choices=["sweep", "grad", "bitflip", "ragged", "schemes"],
                     help="sweep: the throughput sweep (default, the headline line); grad: the differentiable "
                          "layer, complex64 [2048, 4096] forward + backward; bitflip: the fault-coverage campaign; "
@@ -63,7 +63,7 @@ def parse():
 
 def cpu_baseline(sizes):
     """The FP64 oracle (C radix-2, OpenMP over signals) on a bounded sample of
-    the same sweep: 2^22 elements of each size (one signal when N > 2^22)."""
+    the same sweep: 2^23 elements of each size (one signal when N > 2^23)."""
     import numpy as np
 
     import oracle
@@ -75,7 +75,7 @@ def cpu_baseline(sizes):
     nsig_total = 0
     for (dt, k) in sizes:
         n = 1 << k
-        b = max(1, (1 << 22) // n)
+        b = max(1, (1 << 23) // n)
         x = inputs.uniform(inputs.sweep_seed(k, dt == "c128"), b, n, np.complex128)
         t0 = time.perf_counter()
         oracle.fft(x)
@@ -83,8 +83,8 @@ def cpu_baseline(sizes):
         flops += 5.0 * n * k * b
         nsig_total += b
     return {"value": flops / t_total / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 recursive radix-2 oracle, {len(sizes)} sizes of the sweep, 2^22 elements per size "
-                      f"(one signal for N > 2^22; OpenMP over signals), {nsig_total} signals, {t_total:.1f} s",
+            "sample": f"FP64 recursive radix-2 oracle, {len(sizes)} sizes of the sweep, 2^23 elements per size "
+                      f"(one signal for N > 2^23; OpenMP over signals), {nsig_total} signals, {t_total:.1f} s",
             "seconds": t_total}
 
 
@@ -116,13 +116,16 @@ def copy_calibration(log2_bytes):
     print(json.dumps({"copy_bytes": n, "launches": 3}), flush=True)
 
 
-def summarize_pmc(reads_dir, write_dir, copy_log2, label_dt, label_k):
-    """Per-launch HBM traffic of each pass kernel from rocprofv3 --pmc runs.
+def summarize_pmc(root):
+    """Per-launch HBM traffic of the pass kernels from rocprofv3 --pmc runs.
 
-    Reads: the TCC_EA0_RDREQ_{32B,64B,128B} request counts (on gfx950 the
-    derived FETCH_SIZE counts 128-byte requests as 64 bytes).  Writes:
-    WRITE_SIZE (KiB).  Each is scaled by what the same counters read for a
-    plain copy of 2^copy_log2 bytes recorded in the same runs."""
+    ``root`` holds one output directory per run, named <label>_<counter>:
+    label "copy" for a plain device-to-device copy of 2^30 bytes
+    (``--copy-calibration 30``), and "<dtype>_k<k>" for the sweep at one
+    size; counter FETCH_SIZE or WRITE_SIZE (KiB per dispatch).  Each
+    kernel's counter is scaled by bytes / counter of the copy, the same
+    counter, so that the figure is in bytes whatever the counter's unit
+    conventions on this chip."""
     import csv
     import glob
 
@@ -133,31 +136,32 @@ def summarize_pmc(reads_dir, write_dir, copy_log2, label_dt, label_k):
                 rows.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
         return {k: {c: sorted(v)[len(v) // 2] for c, v in cs.items()} for k, cs in rows.items()}
 
-    def read_bytes(c):
-        return (32 * c.get("TCC_EA0_RDREQ_32B_sum", 0) + 64 * c.get("TCC_EA0_RDREQ_64B_sum", 0)
-                + 128 * c.get("TCC_EA0_RDREQ_128B_sum", 0))
-    copy_bytes = 1 << int(copy_log2)
-    reads, writes = read(reads_dir), read(write_dir)
-    iscopy = lambda k: "copybuffer" in k.lower()
-    cr = [read_bytes(c) for k, c in reads.items() if iscopy(k) and read_bytes(c) > 0.5 * copy_bytes]
-    cw = [c["WRITE_SIZE"] * 1024 for k, c in writes.items() if iscopy(k) and "WRITE_SIZE" in c
-          and c["WRITE_SIZE"] * 1024 > 0.5 * copy_bytes]
-    sr = copy_bytes / cr[0] if cr else None
-    sw = copy_bytes / cw[0] if cw else None
+    runs = {}
+    for d in sorted(glob.glob(os.path.join(root, "*_FETCH_SIZE")) + glob.glob(os.path.join(root, "*_WRITE_SIZE"))):
+        base = os.path.basename(d)
+        label, ctr = base.rsplit("_", 2)[0], "_".join(base.rsplit("_", 2)[1:])
+        runs.setdefault(label, {})[ctr] = read(d)
+    copy_bytes = 1 << 30
+    scale = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        vals = [c[ctr] * 1024 for k, c in runs.get("copy", {}).get(ctr, {}).items()
+                if "copybuffer" in k.lower() and ctr in c and c[ctr] * 1024 > 0.25 * copy_bytes]
+        scale[ctr] = copy_bytes / max(vals) if vals else None
     src = os.path.join(ROOT, "paper_2405_02520_amd", "csrc", "tfft_kernels.hip")
     out = {"kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
-           "copy_bytes": copy_bytes, "copy_read_bytes": cr[0] if cr else None,
-           "copy_write_bytes": cw[0] if cw else None, "read_scale": sr, "write_scale": sw, "entries": {}}
-    lines = [f"copy of {copy_bytes} B: reads {out['copy_read_bytes']} B, writes {out['copy_write_bytes']} B "
-             f"-> scales {sr}, {sw}"]
-    label = f"{label_dt}_k{label_k}"
-    for name in sorted(set(reads) & set(writes)):
-        if "pass_kernel" not in name or "WRITE_SIZE" not in writes[name]:
+           "copy_bytes": copy_bytes, "fetch_scale": scale["FETCH_SIZE"], "write_scale": scale["WRITE_SIZE"],
+           "entries": {}}
+    lines = [f"copy of {copy_bytes} B: FETCH_SIZE scale {scale['FETCH_SIZE']}, WRITE_SIZE scale {scale['WRITE_SIZE']}"]
+    for label, ctrs in sorted(runs.items()):
+        if label == "copy" or "FETCH_SIZE" not in ctrs or "WRITE_SIZE" not in ctrs:
             continue
-        f = read_bytes(reads[name]) * (sr or 1.0)
-        w = writes[name]["WRITE_SIZE"] * 1024 * (sw or 1.0)
-        out["entries"][f"{label} {name}"] = {"read_bytes": f, "write_bytes": w, "traffic_bytes": f + w}
-        lines.append(f"{label} {name}: read {f / 2**30:.3f} GiB, write {w / 2**30:.3f} GiB per launch")
+        for name in sorted(set(ctrs["FETCH_SIZE"]) & set(ctrs["WRITE_SIZE"])):
+            if "pass_kernel" not in name:
+                continue
+            f = ctrs["FETCH_SIZE"][name]["FETCH_SIZE"] * 1024 * (scale["FETCH_SIZE"] or 1.0)
+            w = ctrs["WRITE_SIZE"][name]["WRITE_SIZE"] * 1024 * (scale["WRITE_SIZE"] or 1.0)
+            out["entries"][f"{label} {name}"] = {"fetch_bytes": f, "write_bytes": w, "traffic_bytes": f + w}
+            lines.append(f"{label} {name}: fetch {f / 2**30:.3f} GiB, write {w / 2**30:.3f} GiB per launch")
     with open(os.path.join(ROOT, "profiles", "pmc_traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     print("\n".join(lines))
@@ -366,7 +370,7 @@ def main():
     if args.workload == "bitflip":
         return bench_bitflip(args)
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc, args.dtypes, args.kmin)
+        summarize_pmc(args.summarize_pmc)
         return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)

@@ -101,9 +101,14 @@ constexpr int cfg_C(int fp64, int M, int kind) {
 #ifndef TFFT_GRID_MULT
 #define TFFT_GRID_MULT 0
 #endif
-// Streaming (non-temporal) global loads and stores of the signal data.
+// Streaming (non-temporal) global loads and stores of the signal data;
+// multi-pass tiles with rows narrower than TFFT_NT_MIN_ROW bytes store
+// through the cache.
 #ifndef TFFT_NT
 #define TFFT_NT 1
+#endif
+#ifndef TFFT_NT_MIN_ROW
+#define TFFT_NT_MIN_ROW 128
 #endif
 // Total threads of one launch when it is not persistent (workgroups capped
 // at this divided by the workgroup size).

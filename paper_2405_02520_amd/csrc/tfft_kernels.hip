@@ -75,9 +75,9 @@ __device__ __forceinline__ cx<R> ld_stream(const cx<R> *p) {
         return ldg(p);
     }
 }
-template <typename R>
+template <typename R, bool NTS = true>
 __device__ __forceinline__ void st_stream(cx<R> *p, cx<R> a) {
-    if constexpr (TFFT_NT) {
+    if constexpr (TFFT_NT && NTS) {
         nvec2<R> v;
         v.x = a.re;
         v.y = a.im;
@@ -448,6 +448,11 @@ pass_kernel(PassArgs a) {
     constexpr int FP64 = sizeof(R) == 8;
     constexpr bool BLK = FT == FT_BLOCK, SIG = FT == FT_SIGNAL, THR = FT == FT_THREAD;
     constexpr bool PF_FENCE = cfg_pf_fence(FP64, M, KIND) != 0;
+    // Non-temporal stores, except for tiles whose rows are narrower than a
+    // 128-byte line: there the two halves of a line come from different
+    // workgroups and must meet in L2 (measured: streaming them wrote up to
+    // 26% more bytes than the output holds).
+    constexpr bool NT_ST = KIND == KIND_ROWS || cfg_C(FP64, M, KIND) * int(sizeof(cx<R>)) >= TFFT_NT_MIN_ROW;
     constexpr bool ENC = BLK || SIG;  // input and output encodings
     constexpr int E = cfg_E(FP64, M, KIND);
     constexpr int T = M / E;
@@ -802,13 +807,14 @@ pass_kernel(PassArgs a) {
                 cx<R> *base = dst - c + c2;  // rows of one tile share the batch entry
                 if (L.valid) {
 #pragma unroll
-                    for (int m = 0; m < E; ++m) st_stream(base + (uint32_t)(j2 + T * m) * ostr, lds[lidx(c2, j2 + T * m)]);
+                    for (int m = 0; m < E; ++m)
+                        st_stream<R, NT_ST>(base + (uint32_t)(j2 + T * m) * ostr, lds[lidx(c2, j2 + T * m)]);
                 }
                 __syncthreads();
             } else {
                 if (L.valid) {
 #pragma unroll
-                    for (int m = 0; m < E; ++m) st_stream(dst + (uint32_t)(j + T * m) * ostr, d[m]);
+                    for (int m = 0; m < E; ++m) st_stream<R, NT_ST>(dst + (uint32_t)(j + T * m) * ostr, d[m]);
                 }
             }
         }  // rounds
