@@ -142,16 +142,18 @@ constexpr int cfg_pf_fence(int fp64, int M, int kind) {
 }
 constexpr int cfg_threads(int fp64, int M, int kind) { return cfg_C(fp64, M, kind) * (M / cfg_E(fp64, M, kind)); }
 // Prefetch of the next tile straight into a second LDS buffer
-// (global_load_lds_dwordx4: 16-byte elements, i.e. complex128): strided
-// tiles, and row tiles whose members span whole wavefronts (T % 64 == 0),
-// when both buffers fit in 128 KiB.  TFFT_LDSPF64: 0 off, 1 one-pass tiles
-// only, 2 all kinds.
+// (global_load_lds_dwordx4: 16-byte elements, i.e. complex128) for tiles of
+// at least TFFT_LDSPF64_MIN points whose two buffers fit in 128 KiB and
+// whose workgroup is whole wavefronts.  TFFT_LDSPF64: 0 off, 1 one-pass
+// tiles only, 2 all kinds.
 #ifndef TFFT_LDSPF64
 #define TFFT_LDSPF64 2
 #endif
+#ifndef TFFT_LDSPF64_MIN
+#define TFFT_LDSPF64_MIN 16
+#endif
 constexpr int cfg_ldspf(int fp64, int M, int kind) {
-    return (fp64 && (TFFT_LDSPF64 == 2 || (TFFT_LDSPF64 == 1 && kind == KIND_ROWS)) &&
-            (kind == KIND_STRIDED || (M / cfg_E(fp64, M, kind)) % 64 == 0) &&
+    return (fp64 && (TFFT_LDSPF64 == 2 || (TFFT_LDSPF64 == 1 && kind == KIND_ROWS)) && M >= TFFT_LDSPF64_MIN &&
             cfg_C(fp64, M, kind) * M * 16 * 2 <= 131072 && cfg_threads(fp64, M, kind) % 64 == 0)
                ? 1
                : 0;

@@ -577,21 +577,15 @@ pass_kernel(PassArgs a) {
     // from HBM into a second LDS buffer (global_load_lds_dwordx4, no VGPRs
     // held) while the current tile is transformed.  Every thread prefetches
     // its own E elements of its own member; the instruction writes lane l of
-    // a wavefront to slot base + l, so the slots of a thread's element m are
-    // (strided tiles, [pos][slot]) tid + NT m, or (row tiles, [slot][pos],
-    // T a multiple of 64 so a wavefront stays inside one member)
-    // c M + j + T m.  A thread reads back only what its own lane wrote.
+    // a wavefront to slot base + l, so element m of thread tid goes to slot
+    // m NT + tid, and a thread reads back only what its own lane wrote.
     constexpr bool LDSPF = cfg_ldspf(FP64, M, KIND) != 0;
     constexpr bool PREFETCH = !LDSPF && cfg_prefetch(FP64, M, KIND) != 0;
     __shared__ cx<R> nbuf[LDSPF ? C * M : 1];
-    auto nslot = [&](int m) -> int {
-        if constexpr (KIND == KIND_STRIDED) return tid + NT * m;
-        else return c * M + j + T * m;
-    };
+    auto nslot = [&](int m) -> int { return tid + NT * m; };
     auto dma_tile = [&](int64_t gg, int rr) {
         if constexpr (LDSPF) {
-            static_assert(NT % 64 == 0 && sizeof(cx<R>) == 16 && (KIND == KIND_STRIDED || T % 64 == 0),
-                          "LDS prefetch: 16-byte elements, wavefronts inside one member");
+            static_assert(NT % 64 == 0 && sizeof(cx<R>) == 16, "LDS prefetch: 16-byte elements, full wavefronts");
             const MemberLoc Ln = mloc(gg, rr);
             if (gg < n_iter && Ln.valid) {
                 const cx<R> *src = in + Ln.in_off;
@@ -623,9 +617,15 @@ pass_kernel(PassArgs a) {
             cx<R> *dst = out + L.out_off;
             const uint32_t ostr = (uint32_t)L.out_stride;
             cx<R> d[E];
-            // inter-pass twiddle of this member (strided passes), loaded
-            // before any prefetch is issued so that waiting for it never
-            // waits for the prefetch
+            // checksum vector at this thread's positions (when not kept in
+            // registers) and the inter-pass twiddle of this member (strided
+            // passes): loaded before any prefetch is issued, so that waiting
+            // for them never waits for the prefetch
+            cx<double> cl[ENC && !CREG ? E : 1];
+            if constexpr (ENC && !CREG) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) cl[m] = ldg(cv + j + T * m);
+            }
             cx<double> twA{1.0, 0.0}, twB{1.0, 0.0};
             if constexpr (KIND == KIND_STRIDED) {
                 // w_L^{k i} = w_N^{k i N/L}
@@ -666,7 +666,7 @@ pass_kernel(PassArgs a) {
                     const double xr = double(d[m].re), xi = double(d[m].im);
                     cx<double> cm;
                     if constexpr (CREG) cm = cc[m];
-                    else cm = ldg(cv + j + T * m);
+                    else cm = cl[m];
                     lr += cm.re * xr - cm.im * xi;
                     li += cm.re * xi + cm.im * xr;
                     Ssum += d[m].re * d[m].re + d[m].im * d[m].im;
