@@ -1025,25 +1025,35 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
         constexpr int CL = (KIND == KIND_ROWS) ? 1 : C;
         constexpr bool IN_ALONG_MEMBERS = KIND == KIND_STRIDED;
         constexpr bool OUT_ALONG_MEMBERS = KIND != KIND_ROWS;
+        // Members are visited in batches of CU whose loads are all issued
+        // before any is summed (a missing member reads member 0, a valid
+        // location, and contributes zero), so the group's rows stream in
+        // rather than arriving one latency at a time.
+        constexpr int CU = 8;
+        const MemberLoc L0 = member_loc<M, KIND, C>(a, g, 0);
         auto member_sum = [&](bool along_members, int n, auto &&value) -> cx<double> {
             // sum over the members of `value(L, n)`; the calling lanes share n
             // in groups of CL adjacent lanes when along_members
+            const int first = along_members ? tid % CL : 0;
+            const int stride = along_members ? CL : 1;
             cx<double> acc{0.0, 0.0};
-            if (along_members) {
-                const int c = tid % CL;
-                for (int ru = 0; ru * CL < a.G; ++ru) {
-                    const int bm = ru * CL + c;
-                    const MemberLoc L = member_loc<M, KIND, C>(a, g, bm);
-                    if (L.valid) acc = cadd(acc, value(L, bm, n));
+            for (int b0 = first; b0 < a.G; b0 += CU * stride) {
+                cx<double> v[CU];
+#pragma unroll
+                for (int u = 0; u < CU; ++u) {
+                    const int bm = b0 + u * stride;
+                    const MemberLoc Lb = member_loc<M, KIND, C>(a, g, bm < a.G ? bm : 0);
+                    const bool ok = bm < a.G && Lb.valid;
+                    v[u] = value(ok ? Lb : L0, bm, n);
+                    if (!ok) v[u] = cx<double>{0.0, 0.0};
                 }
+#pragma unroll
+                for (int u = 0; u < CU; ++u) acc = cadd(acc, v[u]);
+            }
+            if (along_members) {
                 for (int off = 1; off < CL; off *= 2) {
                     acc.re += __shfl_xor(acc.re, off, 64);
                     acc.im += __shfl_xor(acc.im, off, 64);
-                }
-            } else {
-                for (int bm = 0; bm < a.G; ++bm) {
-                    const MemberLoc L = member_loc<M, KIND, C>(a, g, bm);
-                    if (L.valid) acc = cadd(acc, value(L, bm, n));
                 }
             }
             return acc;
@@ -1092,7 +1102,8 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
             const int k0 = OUT_ALONG_MEMBERS ? tid / CL : tid;
             for (int kk = k0; kk < M; kk += step) {
                 const cx<double> s = member_sum(OUT_ALONG_MEMBERS, kk, [&](const MemberLoc &L, int bm, int k2) {
-                    return bm == jl ? cx<double>{0.0, 0.0} : cmulconj(load_out(L, k2), applied(L, k2));
+                    const cx<double> y = cmulconj(load_out(L, k2), applied(L, k2));
+                    return bm == jl ? cx<double>{0.0, 0.0} : y;
                 });
                 if (!OUT_ALONG_MEMBERS || tid % CL == 0) buf[src ^ 1][kk] = csub(buf[src][kk], s);
             }

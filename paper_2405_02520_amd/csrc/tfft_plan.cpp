@@ -123,10 +123,15 @@ int upload(T **dst, const std::vector<T> &v) {
     return TFFT_OK;
 }
 
+#ifndef TFFT_GROUP_SMALL
+#define TFFT_GROUP_SMALL 64
+#endif
+// One-pass group size: the common path favours large groups (fewer
+// reductions), a correction re-reads the whole group (cost proportional to G).
 int default_group(int M) {
     if (M >= 4096) return 16;
     if (M >= 2048) return 32;
-    return 64;
+    return TFFT_GROUP_SMALL;
 }
 
 // c_n = s sum_k w_3^k w_M^{+-k n}.  Each term is w_{3M}^{k q} with
