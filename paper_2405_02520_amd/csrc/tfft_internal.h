@@ -87,6 +87,12 @@ constexpr int cfg_C(int fp64, int M, int kind) {
 #ifndef TFFT_CREG32
 #define TFFT_CREG32 1
 #endif
+// Stage twiddles not kept in registers come from an LDS octant table (1) or
+// from the L1/L2-resident global table (0); LDS-prefetching kernels always
+// use the LDS table.
+#ifndef TFFT_TWLDS
+#define TFFT_TWLDS 0
+#endif
 #ifndef TFFT_CREG64
 #define TFFT_CREG64 0
 #endif

@@ -491,7 +491,7 @@ pass_kernel(PassArgs a) {
     // first octant, w_M^t for t <= M/8, and the exact symmetries of the
     // table (the host builds it from the same octant): no global load in the
     // transform, whose wait would also wait for the prefetch.
-    constexpr bool TWLDS = cfg_ldspf(FP64, M, KIND) != 0 && M >= 8;
+    constexpr bool TWLDS = !TWREG && (cfg_ldspf(FP64, M, KIND) != 0 || TFFT_TWLDS) && M >= 8;
     __shared__ cx<R> twl[TWLDS ? M / 8 + 1 : 1];
     if constexpr (TWLDS) {
         for (int t = tid; t <= M / 8; t += NT) twl[t] = ldg(stw + t);
