@@ -51,11 +51,12 @@ def parse():
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="turn rocprofv3 --pmc output directories DIR/<label>_<FETCH_SIZE|WRITE_SIZE> (label: copy "
                          "or <dtype>_k<k>) into profiles/pmc_traffic.json")
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "grad", "bitflip", "ragged", "schemes"],
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "grad", "bitflip", "ragged", "schemes", "calibrate"],
                     help="sweep: the throughput sweep (default, the headline line); grad: the differentiable "
                          "layer, complex64 [2048, 4096] forward + backward; bitflip: the fault-coverage campaign; "
                          "ragged: 4096 complex64 signals of lengths 2^U{6..20} in one graph launch; schemes: checksum "
-                         "overhead of the block, one-sided and thread-level schemes, N = 2^8..2^12")
+                         "overhead of the block, one-sided and thread-level schemes, N = 2^8..2^12; calibrate: noise-scaled "
+                         "checksum residuals of >= 10^6 fault-free groups per precision (the threshold factor kappa)")
     ap.add_argument("--ft", default="correct", choices=["off", "detect", "correct"],
                     help="fault-tolerance mode of the timed workload (the headline uses correct)")
     return ap.parse_args()
@@ -214,6 +215,7 @@ def bench_bitflip(args):
     import numpy as np
     import torch
 
+    import paper_2405_02520_amd as tf
     from paper_2405_02520_amd import campaign
     import tfft_inputs as inputs
 
@@ -232,10 +234,12 @@ def bench_bitflip(args):
         mant = 23 if dt == "c64" else 52
         classes = {"mantissa_low": bits < mant // 2, "mantissa_high": (bits >= mant // 2) & (bits < mant),
                    "exponent": (bits >= mant) & (bits < width - 1), "sign": bits == width - 1}
-        det16 = ~(r <= 16.0)
+        with tf.Plan(n, G, dt) as pl:
+            kap = pl.info()["kappa"]
+        det16 = ~(r <= kap)
         out["results"][dt] = {
             "roc_kappa_detection_falsealarm": [[round(k, 3), d, f] for k, d, f in res["roc"][::5]],
-            "at_kappa_16": {"detected_faulty": res["detected_faulty"], "faulty": int(len(faulty)),
+            "at_default_kappa": {"kappa": kap, "detected_faulty": res["detected_faulty"], "faulty": int(len(faulty)),
                             "false_alarms": res["false_alarms"], "clean": int(groups - len(faulty)),
                             "corrected": res["counts"]["corrected"], "uncorrectable": res["counts"]["uncorrectable"]},
             "detection_rate_by_bit_class": {k: (round(float(det16[m].mean()), 4) if m.any() else None)
@@ -359,8 +363,52 @@ def bench_schemes(args):
                                              "U[-1,1), FT correct without faults"}}), flush=True)
 
 
+def bench_calibrate(args):
+    """Threshold calibration: for both precisions, fault-free transforms of
+    N(0,1) and six-decade lognormal inputs at sizes spanning the one-, two- and
+    three-pass plans (2^28 / 2^27 elements each), probed in DETECT mode with a
+    vanishing kappa so that every group reports |d1|; the noise-scaled ratio
+    |d1| / (tau / kappa) of every group is collected until each precision has
+    seen at least 10^6 groups.  kappa must exceed the largest ratio."""
+    import numpy as np
+    import torch
+
+    import paper_2405_02520_amd as tf
+    import tfft_inputs as inputs
+
+    out = {"metric": "noise-scaled checksum residual |d1| / (tau / kappa) of fault-free groups", "results": {}}
+    for dt in args.dtypes.split(","):
+        npdt = np.complex64 if dt == "c64" else np.complex128
+        log2e = args.log2_elems - (0 if dt == "c64" else 1)
+        rows, total, worst, rep = [], 0, 0.0, 0
+        while total < 1_000_000:
+            for k in (8, 10, 12, 13, 14, 16, 18, 19, 20, 22, 24):
+                n = 1 << k
+                b = (1 << log2e) // n
+                for kind in ("gaussian", "dynamic"):
+                    seed = inputs.SEED_PRECISION + 7919 * rep + 31 * k + (1 if kind == "dynamic" else 0)
+                    gen = inputs.device_gaussian if kind == "gaussian" else inputs.device_dynamic
+                    x = gen(seed, b, n, npdt)
+                    probe = tf.Plan(n, b, dt, kappa=1e-12)
+                    probe.forward(x, ft_mode="detect")
+                    c, recs = probe.report()
+                    probe.close()
+                    r = np.array([q.residual / q.threshold * 1e-12 for q in recs if q.threshold > 0])
+                    m = float(r.max()) if r.size else 0.0
+                    rows.append({"k": k, "input": kind, "rep": rep, "groups": c["groups_checked"],
+                                 "max_ratio": round(m, 3), "p99_ratio": round(float(np.quantile(r, 0.99)), 3)})
+                    total += c["groups_checked"]
+                    worst = max(worst, m)
+                    del x
+            rep += 1
+        out["results"][dt] = {"groups": total, "max_ratio": round(worst, 3), "runs": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "calibrate":
+        return bench_calibrate(args)
     if args.workload == "schemes":
         return bench_schemes(args)
     if args.workload == "ragged":

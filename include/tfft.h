@@ -95,7 +95,8 @@ enum tfft_scheme { TFFT_SCHEME_BLOCK = 0, TFFT_SCHEME_SIGNAL = 1, TFFT_SCHEME_TH
 typedef struct {
     uint32_t flags;  /* enum tfft_flags */
     int32_t group;   /* signals per checksum group G (a power of two, 1..64); 0 = default */
-    double kappa;    /* threshold factor; 0 = default (16) */
+    double kappa;    /* threshold factor; 0 = default (16 for complex64, 96 for complex128,
+                        calibrated on fault-free runs) */
     int32_t passes;  /* 0 = automatic; 1, 2 or 3 forces the number of passes (n <= 2^12
                         for 1, 2^8 <= n <= 2^20 for 2, n >= 2^12 for 3); another
                         length gives E_UNSUPPORTED */

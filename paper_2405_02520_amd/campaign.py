@@ -35,10 +35,11 @@ def flip_specs(rng: np.random.Generator, n: int, G: int, groups: int, stages: in
     return specs, faulty
 
 
-def run(x: torch.Tensor, G: int, seed: int, kappa: float = 16.0):
+def run(x: torch.Tensor, G: int, seed: int, kappa: float = 0.0):
     """x: [groups * G, n] complex CUDA tensor (one plan pass, n <= 4096).
-    Returns a dict with the per-group noise-scaled residuals, the ROC, the
-    CORRECT-mode counts and the specs."""
+    ``kappa`` of the CORRECT run: 0 takes the plan's default.  Returns a dict
+    with the per-group noise-scaled residuals, the ROC, the CORRECT-mode
+    counts and the specs."""
     B, n = x.shape
     dtype = "c64" if x.dtype == torch.complex64 else "c128"
     groups = B // G

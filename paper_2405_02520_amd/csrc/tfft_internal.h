@@ -125,6 +125,17 @@ constexpr int cfg_C(int fp64, int M, int kind) {
 #ifndef TFFT_TWO_PASS_MAX_LOG2
 #define TFFT_TWO_PASS_MAX_LOG2 18
 #endif
+// Default threshold factors kappa, calibrated on >= 10^6 fault-free groups
+// per precision (N(0,1) and six-decade lognormal inputs, N = 2^8..2^24): the
+// largest noise-scaled residual |d1| / (tau / kappa) was 8.4 for complex64
+// and 47 for complex128, whose checksum arithmetic (binary64) rounds as
+// coarsely as its data.
+#ifndef TFFT_KAPPA32
+#define TFFT_KAPPA32 16.0
+#endif
+#ifndef TFFT_KAPPA64
+#define TFFT_KAPPA64 96.0
+#endif
 // Parallel branches of a captured ragged graph (independent length classes).
 #ifndef TFFT_GRAPH_BRANCHES
 #define TFFT_GRAPH_BRANCHES 4

@@ -443,7 +443,7 @@ int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_
     p->batch = batch;
     p->dtype = dtype;
     p->flags = flags;
-    p->kappa = (opt && opt->kappa > 0) ? opt->kappa : 16.0;
+    p->kappa = (opt && opt->kappa > 0) ? opt->kappa : (dtype == TFFT_C128 ? TFFT_KAPPA64 : TFFT_KAPPA32);
     p->scheme = scheme;
     p->extent = host_off ? extent : n * batch;
     const int k = ilog2_64(n);

@@ -39,13 +39,17 @@ def test_bitflip_campaign(dtype, tol):
     nrm = np.linalg.norm(ref, axis=1)
     flagged = {r.group for r in res["records"]}
     u = 2.0 ** -24 if dtype == "c64" else 2.0 ** -53
+    from paper_2405_02520_amd import Plan
+
+    with Plan(n, G, dtype) as p:
+        kappa = p.info()["kappa"]  # the CORRECT run's (default) threshold factor
     for f in res["specs"]:
         b = f["signal"]
         g = b // G
         if g in flagged:
             continue
         S = float(np.sum(np.abs(x[g * G:(g + 1) * G].astype(np.complex128)) ** 2))
-        tau = oracle.threshold(n, S, 16.0, u)
+        tau = oracle.threshold(n, S, kappa, u)
         assert err[b] <= tau / (math.sqrt(3) / 2) * math.sqrt(n / 8) + tol * nrm[b]
     faulty_signals = {f["signal"] for f in res["specs"] if f["signal"] // G not in flagged}
     clean = np.array([b for b in range(groups * G) if b not in faulty_signals])

@@ -114,3 +114,32 @@ def ragged_fault_signals(rng: np.random.Generator, lengths, nfaults: int, block:
         raise ValueError(f"{nfaults} faults do not fit in {len(keys)} blocks")
     pick = rng.choice(len(keys), size=nfaults, replace=False)
     return np.sort(np.array([blocks[keys[k]][int(rng.integers(len(blocks[keys[k]])))] for k in pick], np.int64))
+
+
+def device_gaussian(seed: int, batch: int, n: int, dtype, device="cuda"):
+    """Like ``gaussian`` but drawn on the device with torch's generator seeded
+    by ``seed`` (for large fault-free calibration runs that no oracle checks):
+    re and im i.i.d. N(0, 1)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    real = torch.float32 if dtype in (np.complex64, "c64") else torch.float64
+    re = torch.randn((batch, n), generator=g, device=device, dtype=real)
+    im = torch.randn((batch, n), generator=g, device=device, dtype=real)
+    return torch.complex(re, im)
+
+
+def device_dynamic(seed: int, batch: int, n: int, dtype, device="cuda"):
+    """Like ``dynamic`` (six-decade lognormal magnitudes, uniform phases), drawn
+    on the device with torch's generator seeded by ``seed``."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    real = torch.float64
+    sigma = math.log(1e6) / 6.0
+    mag = torch.exp(sigma * torch.randn((batch, n), generator=g, device=device, dtype=real))
+    phase = 2.0 * math.pi * torch.rand((batch, n), generator=g, device=device, dtype=real)
+    z = torch.polar(mag, phase)
+    return z.to(torch.complex64 if dtype in (np.complex64, "c64") else torch.complex128)
