@@ -144,6 +144,10 @@ constexpr int cfg_twreg(int fp64, int M, int kind) { return fp64 ? TFFT_TWREG64 
 constexpr int cfg_creg(int fp64, int M, int kind) { return fp64 ? TFFT_CREG64 : TFFT_CREG32; }
 // Issue the next tile's loads before transforming the current one.
 constexpr int cfg_prefetch(int fp64, int M, int kind) { return fp64 ? TFFT_PREFETCH64 : TFFT_PREFETCH32; }
+// Deferred stores in LDS-prefetching one-pass kernels (see the pass kernel).
+#ifndef TFFT_DEFER_ST
+#define TFFT_DEFER_ST 1
+#endif
 // Order the register prefetch after the current tile's values are in
 // registers, with branch-free tile loads (see the pass kernel): multi-pass
 // tiles, and one-pass tiles of at least TFFT_PF_FENCE_ROWS_MIN points

@@ -601,6 +601,23 @@ pass_kernel(PassArgs a) {
     };
     if constexpr (PREFETCH) load_tile(wl, 0);
     if constexpr (LDSPF) dma_tile(wl, 0);
+    // Deferred stores (LDS-prefetching row tiles): a tile's outputs stay in
+    // registers and are stored right after the next tile's prefetch has been
+    // waited for, so that the wait (which also counts stores) never waits
+    // for stores issued just before it.
+    constexpr bool DEFER = LDSPF && KIND == KIND_ROWS && TFFT_DEFER_ST;
+    cx<R> ps[DEFER ? E : 1];
+    cx<R> *pdst = out;
+    bool pend = false;
+    auto flush = [&]() {
+        if constexpr (DEFER) {
+            if (pend) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) st_stream<R, NT_ST>(pdst + (uint32_t)(j + T * m), ps[m]);
+            }
+            pend = false;
+        }
+    };
     for (int64_t g = wl; g < n_iter; g += nwg) {
         const int64_t gsig = g * C + c;  // FT_SIGNAL: this thread's signal (= its group)
         // the fault lookup reads a table entry or a constant -1 (no branch)
@@ -636,6 +653,7 @@ pass_kernel(PassArgs a) {
                 // this tile's DMA (issued one iteration earlier) has landed;
                 // each thread reads only the slots its own lane filled
                 asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                flush();
 #pragma unroll
                 for (int m = 0; m < E; ++m) d[m] = L.valid ? nbuf[nslot(m)] : cx<R>{R(0), R(0)};
                 // (the next DMA is issued after the input encoding below, so
@@ -811,6 +829,11 @@ pass_kernel(PassArgs a) {
                         st_stream<R, NT_ST>(base + (uint32_t)(j2 + T * m) * ostr, lds[lidx(c2, j2 + T * m)]);
                 }
                 __syncthreads();
+            } else if constexpr (DEFER) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) ps[m] = d[m];
+                pdst = dst;
+                pend = L.valid;
             } else {
                 if (L.valid) {
 #pragma unroll
@@ -924,6 +947,7 @@ pass_kernel(PassArgs a) {
             __syncthreads();
         }
     }  // groups
+    flush();
 }
 
 // ------------------------------------------------------- correction kernel
