@@ -144,10 +144,15 @@ constexpr int cfg_twreg(int fp64, int M, int kind) { return fp64 ? TFFT_TWREG64 
 constexpr int cfg_creg(int fp64, int M, int kind) { return fp64 ? TFFT_CREG64 : TFFT_CREG32; }
 // Issue the next tile's loads before transforming the current one.
 constexpr int cfg_prefetch(int fp64, int M, int kind) { return fp64 ? TFFT_PREFETCH64 : TFFT_PREFETCH32; }
-// Deferred stores in LDS-prefetching one-pass kernels (see the pass kernel).
+// Deferred stores (see the pass kernel): 0 never, 1 in LDS-prefetching
+// one-pass kernels, 2 in every prefetching kernel (measured: 2-8% slower on
+// the multi-pass sizes, where the kept registers cost more than the wait).
 #ifndef TFFT_DEFER_ST
 #define TFFT_DEFER_ST 1
 #endif
+constexpr bool cfg_defer(int fp64, int M, int kind) {
+    return TFFT_DEFER_ST == 2 || (TFFT_DEFER_ST == 1 && fp64 && kind == KIND_ROWS);
+}
 // Order the register prefetch after the current tile's values are in
 // registers, with branch-free tile loads (see the pass kernel): multi-pass
 // tiles, and one-pass tiles of at least TFFT_PF_FENCE_ROWS_MIN points

@@ -605,15 +605,16 @@ pass_kernel(PassArgs a) {
     // registers and are stored right after the next tile's prefetch has been
     // waited for, so that the wait (which also counts stores) never waits
     // for stores issued just before it.
-    constexpr bool DEFER = LDSPF && KIND == KIND_ROWS && TFFT_DEFER_ST;
+    constexpr bool DEFER = cfg_defer(FP64, M, KIND) && (LDSPF || (PREFETCH && PF_FENCE));
     cx<R> ps[DEFER ? E : 1];
-    cx<R> *pdst = out;
+    cx<R> *pdst = out;     // first element of the pending stores
+    uint32_t pstr = 1;     // their stride
     bool pend = false;
     auto flush = [&]() {
         if constexpr (DEFER) {
             if (pend) {
 #pragma unroll
-                for (int m = 0; m < E; ++m) st_stream<R, NT_ST>(pdst + (uint32_t)(j + T * m), ps[m]);
+                for (int m = 0; m < E; ++m) st_stream<R, NT_ST>(pdst + (uint32_t)(T * m) * pstr, ps[m]);
             }
             pend = false;
         }
@@ -670,6 +671,7 @@ pass_kernel(PassArgs a) {
                     for (int m = 0; m < E; ++m) asm volatile("" : "+v"(d[m].re), "+v"(d[m].im));
                     asm volatile("" ::: "memory");
                 }
+                flush();
                 if (r + 1 < rounds) load_tile(g, r + 1);
                 else load_tile(g + nwg, 0);
             } else {
@@ -823,7 +825,13 @@ pass_kernel(PassArgs a) {
                 __syncthreads();
                 const int c2 = tid % C, j2 = tid / C;
                 cx<R> *base = dst - c + c2;  // rows of one tile share the batch entry
-                if (L.valid) {
+                if constexpr (DEFER) {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) ps[m] = lds[lidx(c2, j2 + T * m)];
+                    pdst = base + (uint32_t)j2 * ostr;
+                    pstr = ostr;
+                    pend = L.valid;
+                } else if (L.valid) {
 #pragma unroll
                     for (int m = 0; m < E; ++m)
                         st_stream<R, NT_ST>(base + (uint32_t)(j2 + T * m) * ostr, lds[lidx(c2, j2 + T * m)]);
@@ -832,7 +840,8 @@ pass_kernel(PassArgs a) {
             } else if constexpr (DEFER) {
 #pragma unroll
                 for (int m = 0; m < E; ++m) ps[m] = d[m];
-                pdst = dst;
+                pdst = dst + (uint32_t)j * ostr;
+                pstr = ostr;
                 pend = L.valid;
             } else {
                 if (L.valid) {
