@@ -121,9 +121,14 @@ constexpr int cfg_C(int fp64, int M, int kind) {
 #ifndef TFFT_GRID_THREADS
 #define TFFT_GRID_THREADS (4096 * 256)
 #endif
-// Largest log2(N) planned with two passes (three passes above).
-#ifndef TFFT_TWO_PASS_MAX_LOG2
-#define TFFT_TWO_PASS_MAX_LOG2 18
+// Largest log2(N) planned with two passes (three passes above), per element
+// type (measured: complex64 N = 2^20 as 1024 x 1024 has 32-byte tile rows in
+// its first pass and is faster in three).
+#ifndef TFFT_TWO_PASS_MAX_LOG2_32
+#define TFFT_TWO_PASS_MAX_LOG2_32 19
+#endif
+#ifndef TFFT_TWO_PASS_MAX_LOG2_64
+#define TFFT_TWO_PASS_MAX_LOG2_64 20
 #endif
 // Default threshold factors kappa, calibrated on >= 10^6 fault-free groups
 // per precision (N(0,1) and six-decade lognormal inputs, N = 2^8..2^24): the

@@ -448,10 +448,11 @@ int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_
     p->extent = host_off ? extent : n * batch;
     const int k = ilog2_64(n);
     int rc = TFFT_OK;
-    // one pass up to 2^12; two passes up to 2^TFFT_TWO_PASS_MAX_LOG2; three
+    // one pass up to 2^12; two passes up to 2^19 (complex64) / 2^20; three
     // passes above, the shortest first (tiles of the strided passes then hold
     // >= 16 adjacent sub-signals, i.e. >= 128-byte segments per row)
-    const int npass = force_passes ? force_passes : (k <= 12 ? 1 : (k <= TFFT_TWO_PASS_MAX_LOG2 ? 2 : 3));
+    const int two_max = dtype == TFFT_C128 ? TFFT_TWO_PASS_MAX_LOG2_64 : TFFT_TWO_PASS_MAX_LOG2_32;
+    const int npass = force_passes ? force_passes : (k <= 12 ? 1 : (k <= two_max ? 2 : 3));
     if (npass == 1) {
         p->passes = 1;
         p->lens[0] = (int)n;
