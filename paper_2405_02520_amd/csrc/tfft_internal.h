@@ -149,6 +149,15 @@ constexpr int cfg_twreg(int fp64, int M, int kind) { return fp64 ? TFFT_TWREG64 
 constexpr int cfg_creg(int fp64, int M, int kind) { return fp64 ? TFFT_CREG64 : TFFT_CREG32; }
 // Issue the next tile's loads before transforming the current one.
 constexpr int cfg_prefetch(int fp64, int M, int kind) { return fp64 ? TFFT_PREFETCH64 : TFFT_PREFETCH32; }
+// Correction launch: at most TFFT_CORRECT_GRID workgroups (one per record,
+// the rest exit at once), each summing group members TFFT_CORRECT_BATCH at a
+// time.
+#ifndef TFFT_CORRECT_GRID
+#define TFFT_CORRECT_GRID 1024
+#endif
+#ifndef TFFT_CORRECT_BATCH
+#define TFFT_CORRECT_BATCH 8
+#endif
 // Deferred stores (see the pass kernel): 0 never, 1 in LDS-prefetching
 // one-pass kernels, 2 in every prefetching kernel (measured: 2-8% slower on
 // the multi-pass sizes, where the kept registers cost more than the wait).

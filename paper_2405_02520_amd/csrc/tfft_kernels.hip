@@ -273,8 +273,37 @@ __device__ __forceinline__ double flip_bits(double v, unsigned long long mask) {
 }
 
 template <typename R, int E>
+__device__ __forceinline__ void apply_hit(cx<R> (&d)[E], const FaultHit &h);
+
+template <typename R, int E>
 __device__ __forceinline__ void apply_faults(cx<R> (&d)[E], const DevFault *F, int fh, int stage, int b, int j) {
-    const FaultHit h = find_fault(F, fh, stage, b, j);
+    apply_hit<R, E>(d, find_fault(F, fh, stage, b, j));
+}
+
+// The usual case of one fault in the group: its spec is read once per group
+// (f0) and each stage only compares, instead of walking the list in global
+// memory after every stage.
+template <typename R, int E>
+__device__ __forceinline__ void apply_faults_g(cx<R> (&d)[E], const DevFault &f0, bool multi, const DevFault *F,
+                                               int fh, int stage, int b, int j) {
+    if (multi) {
+        apply_faults<R, E>(d, F, fh, stage, b, j);
+    } else if (f0.stage == stage && f0.member == b && f0.j == j) {
+        FaultHit h{f0.m, 0.0, 0.0, 0ull, 0ull};
+        if (f0.mode == 0) {
+            h.dre = f0.dre;
+            h.dim = f0.dim;
+        } else if (f0.mode == 1) {
+            h.fre = 1ull << f0.bit;
+        } else {
+            h.fim = 1ull << f0.bit;
+        }
+        apply_hit<R, E>(d, h);
+    }
+}
+
+template <typename R, int E>
+__device__ __forceinline__ void apply_hit(cx<R> (&d)[E], const FaultHit &h) {
     // Every register takes an addend and a flip mask that are zero except at
     // h.m: written as an add of a selected value and an xor with a selected
     // mask (not a conditional update) so the compiler cannot turn it into an
@@ -626,6 +655,18 @@ pass_kernel(PassArgs a) {
         if constexpr (SIG) fhp = (a.fault_head && gsig < a.n_groups) ? a.fault_head + gsig : &kNoFault;
         else fhp = a.fault_head ? a.fault_head + g : &kNoFault;
         const int fh = *fhp;
+        // the group's first fault, staged in LDS once (fh is uniform outside
+        // FT_SIGNAL, whose threads walk the list themselves)
+        __shared__ DevFault f0;
+        bool fmulti = true;
+        if constexpr (!SIG) {
+            if (fh >= 0) {
+                __syncthreads();
+                if (tid == 0) f0 = a.faults[fh];
+                __syncthreads();
+                fmulti = f0.next >= 0;
+            }
+        }
         double D1r = 0.0, D1i = 0.0, D2r = 0.0, D2i = 0.0;
         R Ssum = R(0);  // energy of the group's inputs, for the threshold only
         for (int r = 0; r < rounds; ++r) {
@@ -740,10 +781,10 @@ pass_kernel(PassArgs a) {
                     static_for<0, RAD>([&](auto q) { d[p + q * NB] = v[q]; });
                 });
                 if (fh >= 0) {
-                    apply_faults<R, E>(d, a.faults, fh, s, b, j);
+                    apply_faults_g<R, E>(d, f0, fmulti, a.faults, fh, s, b, j);
                     // FT_THREAD has no output encoding: a fault on a final
                     // value lands on the last butterfly's output
-                    if constexpr (THR && s == NSTAGE - 1) apply_faults<R, E>(d, a.faults, fh, -1, b, j);
+                    if constexpr (THR && s == NSTAGE - 1) apply_faults_g<R, E>(d, f0, fmulti, a.faults, fh, -1, b, j);
                 }
                 if constexpr (THR) {
                     static_for<0, NB>([&](auto p) {
@@ -785,7 +826,7 @@ pass_kernel(PassArgs a) {
                 }
             }
             if constexpr (!THR) {
-                if (fh >= 0) apply_faults<R, E>(d, a.faults, fh, -1, b, j);
+                if (fh >= 0) apply_faults_g<R, E>(d, f0, fmulti, a.faults, fh, -1, b, j);
             }
             if constexpr (ENC) {
                 double Ar[3] = {0.0, 0.0, 0.0}, Ai[3] = {0.0, 0.0, 0.0};
@@ -1062,7 +1103,7 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
         // before any is summed (a missing member reads member 0, a valid
         // location, and contributes zero), so the group's rows stream in
         // rather than arriving one latency at a time.
-        constexpr int CU = 8;
+        constexpr int CU = TFFT_CORRECT_BATCH;
         const MemberLoc L0 = member_loc<M, KIND, C>(a, g, 0);
         auto member_sum = [&](bool along_members, int n, auto &&value) -> cx<double> {
             // sum over the members of `value(L, n)`; the calling lanes share n

@@ -367,9 +367,9 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
         if (launch_pass(fp64, P.M, P.kind, scheme_ft, A, P.grid, st) != hipSuccess) return TFFT_E_HIP;
         if (timed && hipEventRecord(p->ev[1 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
         if (mode == TFFT_FT_CORRECT && p->scheme != TFFT_SCHEME_THREAD) {
-            // one workgroup per possible record, at most 1024; a workgroup
+            // one workgroup per possible record, at most TFFT_CORRECT_GRID; a workgroup
             // with no record of this pass exits at once
-            const int cgrid = (int)std::min<int64_t>(1024, std::max<int64_t>(1, P.n_groups));
+            const int cgrid = (int)std::min<int64_t>(TFFT_CORRECT_GRID, std::max<int64_t>(1, P.n_groups));
             if (launch_correct(fp64, P.M, P.kind, A, cgrid, st) != hipSuccess) return TFFT_E_HIP;
         }
         if (timed && hipEventRecord(p->ev[2 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
