@@ -236,14 +236,26 @@ int tfft_get_timings(tfft_plan p, double *pass_ms, double *correct_ms);
  * ------------------------------------------------------------------------ */
 typedef struct tfft_ragged_s *tfft_ragged;
 
+/* Create a ragged plan on the current device.  lengths[count] and
+ * offsets[count] are host arrays (copied; the caller keeps ownership);
+ * dtype as for tfft_plan_create; opt as for tfft_plan_create_with (applied
+ * to every class), may be NULL.  E_INVALID: count < 1, a length that is not a
+ * power of two in 2..2^24, a negative offset, overlapping signals, a bad
+ * dtype or option; E_NOMEM / E_HIP as for plans.  *out is NULL on failure. */
 int tfft_ragged_create(tfft_ragged *out, int64_t count, const int64_t *lengths, const int64_t *offsets, int dtype,
                        const tfft_options *opt);
+/* Free the plans, graphs and streams of r (NULL-safe). */
 int tfft_ragged_destroy(tfft_ragged r);
 
-/* Transform every signal (forward, or inverse when inverse != 0).  With
- * use_graph != 0 all launches of all classes are captured once into a HIP
- * graph (per buffers, mode and direction) and replayed as one graph launch;
- * hip_stream must then be a non-null stream.  Asynchronous. */
+/* Transform every signal (forward, or inverse when inverse != 0) from the
+ * device buffer d_in to d_out, each at least max(offsets[i] + lengths[i])
+ * elements, 16-byte aligned, not overlapping each other; elements outside
+ * every signal are left untouched in d_out.  ft_mode as for
+ * tfft_exec_forward.  With use_graph != 0 all launches of all classes are
+ * captured once into a HIP graph (per buffers, mode, direction and stream;
+ * the classes run on parallel branches) and replayed as one graph launch;
+ * hip_stream must then be a non-null stream.  Asynchronous; E_INVALID for
+ * NULL or misaligned pointers, E_HIP for a failed launch or capture. */
 int tfft_ragged_exec(tfft_ragged r, const void *d_in, void *d_out, int ft_mode, int inverse, int use_graph,
                      void *hip_stream);
 
@@ -253,10 +265,13 @@ int tfft_ragged_get_report(tfft_ragged r, tfft_counts *counts, tfft_record *recs
 /* Test hook; specs[k].signal is the ragged index. */
 int tfft_ragged_set_faults(tfft_ragged r, const tfft_fault *specs, int64_t n);
 
-/* Autotuner: for each length class, time the candidate plans (pass count,
- * checksum group size, workgroups per launch) on the given buffers with
- * fault tolerance CORRECT, `reps` executions each, and keep the fastest.
- * Synchronous on hip_stream; invalidates captured graphs. */
+/* Autotuner (the semi-empirical choice of per-size parameters, TurboFFT
+ * Sec. IV-B.3 and Table I, made by measurement): for each length class, time
+ * the candidate plans (pass count, checksum group size, workgroups per
+ * launch) on the given buffers with fault tolerance CORRECT, `reps`
+ * executions each after one warm-up, and keep the fastest.  Overwrites
+ * d_out.  Synchronous on hip_stream; drops captured graphs and injected
+ * faults (the classes get new plans). */
 int tfft_ragged_tune(tfft_ragged r, const void *d_in, void *d_out, void *hip_stream, int reps);
 
 /* Classes of the ragged plan: their count in *classes and, for the first
