@@ -158,6 +158,12 @@ constexpr int cfg_prefetch(int fp64, int M, int kind) { return fp64 ? TFFT_PREFE
 #ifndef TFFT_CORRECT_BATCH
 #define TFFT_CORRECT_BATCH 8
 #endif
+// Group sums of the two-sided checksum reduced through LDS by one wavefront
+// (1) or by DPP in every wavefront (0; measured faster: the LDS variant's two
+// extra barriers per group cost more than the DPP instructions it saves).
+#ifndef TFFT_LDS_RED
+#define TFFT_LDS_RED 0
+#endif
 // Deferred stores (see the pass kernel): 0 never, 1 in LDS-prefetching
 // one-pass kernels, 2 in every prefetching kernel (measured: 2-8% slower on
 // the multi-pass sizes, where the kept registers cost more than the wait).

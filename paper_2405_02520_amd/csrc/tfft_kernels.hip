@@ -491,6 +491,9 @@ pass_kernel(PassArgs a) {
     constexpr int NSTAGE = St::count;
     constexpr int WAVES = (NT + 63) / 64;
     constexpr int WIDTH = NT < 64 ? NT : 64;
+    // group sums reduced through LDS (see the end of a group)
+    constexpr bool LDS_RED = TFFT_LDS_RED && NT % 64 == 0 && NT > 64 &&
+                             C * M * int(sizeof(cx<R>)) >= 5 * NT * int(sizeof(double));
 
     __shared__ cx<R> lds[C * M];
     __shared__ double red[WAVES][5];
@@ -936,31 +939,8 @@ pass_kernel(PassArgs a) {
             if constexpr (T > 64) __syncthreads();
         }
         if constexpr (BLK) {
-            double v[5] = {D1r, D1i, D2r, D2i, 0.0};
-            if constexpr (NT % 64 == 0) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = wave_sum_dpp(v[q], Dpp64{});
-                float sf = float(Ssum);
-                if constexpr (sizeof(R) == 8) v[4] = wave_sum_dpp(double(Ssum), Dpp64{});
-                else v[4] = double(wave_sum_dpp(sf, Dpp32{}));
-                if ((tid & 63) == 63) {
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) red[tid >> 6][q] = v[q];
-                }
-            } else {
-                v[4] = double(Ssum);
-#pragma unroll
-                for (int q = 0; q < 5; ++q) v[q] = wave_sum(v[q], WIDTH);
-                if ((tid & 63) == 0) {
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) red[tid >> 6][q] = v[q];
-                }
-            }
-            __syncthreads();
-            if (tid == 0) {
-                double t[5] = {0, 0, 0, 0, 0};
-                for (int w = 0; w < WAVES; ++w)
-                    for (int k = 0; k < 5; ++k) t[k] += red[w][k];
+            // the group's decision from its five sums (one thread)
+            auto decide = [&](const double *t) {
                 const double d1r = t[0], d1i = t[1], d2r = t[2], d2i = t[3], S = t[4];
                 const double tau = a.tau_coef * sqrt(S);
                 const double ad1 = sqrt(d1r * d1r + d1i * d1i);
@@ -993,8 +973,60 @@ pass_kernel(PassArgs a) {
                         a.recs[slot] = rc;
                     }
                 }
+            };
+            if constexpr (LDS_RED) {
+                // partial sums through the (now idle) exchange buffer, added
+                // up by one wavefront: each thread stores five values instead
+                // of running five 64-bit DPP reductions
+                double *part = reinterpret_cast<double *>(lds);
+                __syncthreads();
+                part[tid] = D1r;
+                part[NT + tid] = D1i;
+                part[2 * NT + tid] = D2r;
+                part[3 * NT + tid] = D2i;
+                part[4 * NT + tid] = double(Ssum);
+                __syncthreads();
+                if (tid < 64) {
+                    double v[5];
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) {
+                        v[q] = 0.0;
+                        for (int w = tid; w < NT; w += 64) v[q] += part[q * NT + w];
+                        v[q] = wave_sum_dpp(v[q], Dpp64{});
+                    }
+                    if (tid == 63) decide(v);
+                }
+                __syncthreads();
+            } else {
+                double v[5] = {D1r, D1i, D2r, D2i, 0.0};
+                if constexpr (NT % 64 == 0) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v[q] = wave_sum_dpp(v[q], Dpp64{});
+                    float sf = float(Ssum);
+                    if constexpr (sizeof(R) == 8) v[4] = wave_sum_dpp(double(Ssum), Dpp64{});
+                    else v[4] = double(wave_sum_dpp(sf, Dpp32{}));
+                    if ((tid & 63) == 63) {
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) red[tid >> 6][q] = v[q];
+                    }
+                } else {
+                    v[4] = double(Ssum);
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) v[q] = wave_sum(v[q], WIDTH);
+                    if ((tid & 63) == 0) {
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) red[tid >> 6][q] = v[q];
+                    }
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    double t[5] = {0, 0, 0, 0, 0};
+                    for (int w = 0; w < WAVES; ++w)
+                        for (int k = 0; k < 5; ++k) t[k] += red[w][k];
+                    decide(t);
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }  // groups
     flush();
