@@ -55,7 +55,7 @@ def parse():
                     help="sweep: the throughput sweep (default, the headline line); grad: the differentiable "
                          "layer, complex64 [2048, 4096] forward + backward; bitflip: the fault-coverage campaign; "
                          "ragged: 4096 complex64 signals of lengths 2^U{6..20} in one graph launch; schemes: checksum "
-                         "overhead of the block, one-sided and thread-level schemes, N = 2^8..2^12; calibrate: noise-scaled "
+                         "overhead of the block, one-sided and thread-level schemes, N = 2^8..2^16; calibrate: noise-scaled "
                          "checksum residuals of >= 10^6 fault-free groups per precision (the threshold factor kappa)")
     ap.add_argument("--ft", default="correct", choices=["off", "detect", "correct"],
                     help="fault-tolerance mode of the timed workload (the headline uses correct)")
@@ -316,9 +316,10 @@ def bench_ragged(args):
 
 def bench_schemes(args):
     """Checksum overhead by granularity (the comparison of one-sided,
-    thread-level two-sided and threadblock-level two-sided schemes): single-pass
-    sizes N = 2^8..2^12, 2^28 (complex64) / 2^27 (complex128) elements, FT
-    CORRECT without faults against FT OFF on the same kernels."""
+    thread-level two-sided and threadblock-level two-sided schemes): N =
+    2^8..2^16 (the one-sided scheme up to 2^12), 2^28 (complex64) / 2^27
+    (complex128) elements, FT CORRECT without faults against FT OFF on the
+    same kernels."""
     import numpy as np
     import torch
 
@@ -330,13 +331,14 @@ def bench_schemes(args):
     for dt in args.dtypes.split(","):
         npdt = np.complex64 if dt == "c64" else np.complex128
         total = 1 << (args.log2_elems - (0 if dt == "c64" else 1))
-        for k in range(max(8, args.kmin), min(12, args.kmax) + 1):
+        for k in range(max(8, args.kmin), min(16, args.kmax) + 1):
             n = 1 << k
             B = total // n
             xd = torch.from_numpy(inputs.uniform(inputs.sweep_seed(k, dt == "c128"), B, n, npdt)).cuda()
             out = torch.empty_like(xd)
             ms = {}
-            for scheme in ("block", "signal", "thread"):
+            schemes = ("block", "signal", "thread") if k <= 12 else ("block", "thread")
+            for scheme in schemes:
                 plan = tf.Plan(n, B, dt, scheme=scheme)
                 for mode in (["off"] if scheme == "block" else []) + ["correct"]:
                     with torch.cuda.stream(st):
@@ -353,14 +355,15 @@ def bench_schemes(args):
                 plan.close()
             rows.append({"dtype": dt, "n": n, "batch": B, "ms_off": round(ms["off"], 4),
                          **{f"overhead_pct_{s}": round((ms[s] / ms["off"] - 1) * 100, 2)
-                            for s in ("block", "signal", "thread")},
+                            for s in schemes},
                          "GBps_block": round(2 * total * (8 if dt == "c64" else 16) / (ms["block"] * 1e-3) / 1e9, 1)})
             del xd, out
-    mean = {s: round(float(np.mean([r[f"overhead_pct_{s}"] for r in rows])), 2) for s in ("block", "signal", "thread")}
+    mean = {s: round(float(np.mean([r[f"overhead_pct_{s}"] for r in rows if f"overhead_pct_{s}" in r])), 2)
+            for s in ("block", "signal", "thread")}
     print(json.dumps({"metric": "checksum overhead % vs FT off, by scheme granularity", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "mean_overhead_pct": mean, "sizes": rows,
-                      "config": {"workload": "forward C2C, N = 2^8..2^12, N*batch = 2^28 (c64) / 2^27 (c128), "
-                                             "U[-1,1), FT correct without faults"}}), flush=True)
+                      "config": {"workload": "forward C2C, N = 2^8..2^16 (one-sided scheme up to 2^12), N*batch = 2^28 (c64) "
+                                             "/ 2^27 (c128), U[-1,1), FT correct without faults"}}), flush=True)
 
 
 def bench_calibrate(args):

@@ -88,7 +88,8 @@ enum tfft_locate { TFFT_LOC_NONE = 0, TFFT_LOC_QUOTIENT = 1, TFFT_LOC_PER_SIGNAL
  *   THREAD - two-sided checks of every radix butterfly inside the thread that
  *            computes it (two transform encodings e and (k+1) e locate the
  *            wrong output); a flagged butterfly is recomputed in registers.
- *            Protects the butterflies only, not the data between them. */
+ *            Protects the butterflies only, not the data between them nor
+ *            the inter-pass twiddles of multi-pass plans. */
 enum tfft_scheme { TFFT_SCHEME_BLOCK = 0, TFFT_SCHEME_SIGNAL = 1, TFFT_SCHEME_THREAD = 2 };
 
 /* Options for tfft_plan_create_with.  Zero fields take the defaults. */
@@ -102,7 +103,7 @@ typedef struct {
                         length gives E_UNSUPPORTED */
     int32_t grid_scale; /* 0 = default; else workgroups per launch = default * 2^grid_scale
                            (-3..3), a tuning knob */
-    int32_t scheme;  /* enum tfft_scheme; schemes other than BLOCK need n <= 2^12 (one pass) */
+    int32_t scheme;  /* enum tfft_scheme; SIGNAL needs n <= 2^12 (one pass) */
     int32_t reserved[5];
 } tfft_options;
 

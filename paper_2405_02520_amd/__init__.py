@@ -158,8 +158,8 @@ class Plan:
     def __init__(self, n: int, batch: int, dtype="c64", group: int = 0, kappa: float = 0.0,
                  inverse_unscaled: bool = False, passes: int = 0, grid_scale: int = 0, scheme="block"):
         """scheme: "block" (two-sided, per group of signals), "signal"
-        (one-sided, per signal) or "thread" (per radix butterfly); the last
-        two for n <= 4096."""
+        (one-sided, per signal; n <= 4096) or "thread" (per radix
+        butterfly)."""
         self.n, self.batch = int(n), int(batch)
         self.dtype_code = _dtype_code(dtype)
         sch = _SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)

@@ -470,7 +470,7 @@ __device__ __forceinline__ void thread_check(cx<R> (&d)[E], const cx<R> (&vin)[E
 // FT_SIGNAL (one-sided: one residual per signal, reduced over the signal's
 // threads; a flagged signal is recomputed) or FT_THREAD (two-sided checks of
 // every radix butterfly inside the thread that computes it, corrected in
-// registers).  FT_SIGNAL and FT_THREAD exist for single-pass plans.
+// registers).  FT_SIGNAL exists for single-pass plans.
 template <typename R, int M, int KIND, int FT>
 __global__ void __launch_bounds__(cfg_threads(sizeof(R) == 8, M, KIND))
 pass_kernel(PassArgs a) {
@@ -1264,9 +1264,9 @@ template <typename R, int M, int KIND>
 static hipError_t launch_kind(int ft, const PassArgs &a, int grid, hipStream_t st) {
     if (ft == FT_BLOCK) return launch_one<R, M, KIND, FT_BLOCK>(a, grid, st);
     if (ft == FT_NONE) return launch_one<R, M, KIND, FT_NONE>(a, grid, st);
+    if (ft == FT_THREAD) return launch_one<R, M, KIND, FT_THREAD>(a, grid, st);
     if constexpr (KIND == KIND_ROWS) {
         if (ft == FT_SIGNAL) return launch_one<R, M, KIND, FT_SIGNAL>(a, grid, st);
-        if (ft == FT_THREAD) return launch_one<R, M, KIND, FT_THREAD>(a, grid, st);
     }
     return hipErrorInvalidValue;
 }

@@ -426,8 +426,9 @@ int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_
     const int scheme = opt ? opt->scheme : TFFT_SCHEME_BLOCK;
     if (force_passes < 0 || force_passes > 3 || grid_scale < -3 || grid_scale > 3) return TFFT_E_INVALID;
     if (scheme < TFFT_SCHEME_BLOCK || scheme > TFFT_SCHEME_THREAD) return TFFT_E_INVALID;
-    // the one-sided and thread-level schemes exist for single-pass plans
-    if (scheme != TFFT_SCHEME_BLOCK && (ilog2_64(n) > 12 || force_passes > 1)) return TFFT_E_UNSUPPORTED;
+    // the one-sided scheme exists for single-pass plans; the alternative
+    // schemes are not offered for ragged classes
+    if (scheme == TFFT_SCHEME_SIGNAL && (ilog2_64(n) > 12 || force_passes > 1)) return TFFT_E_UNSUPPORTED;
     if (scheme != TFFT_SCHEME_BLOCK && host_off) return TFFT_E_UNSUPPORTED;
     {
         const int kk = ilog2_64(n);

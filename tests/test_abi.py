@@ -136,8 +136,7 @@ def test_scheme_option_validation(tf):
     for scheme in (-1, 3):
         opt = tf.tfft_options(scheme=scheme)
         assert tf.tfft_plan_create_with(ctypes.byref(h), 1024, 4, 0, ctypes.byref(opt)) == tf.E_INVALID
-    # the one-sided and thread-level schemes are single-pass only
-    for scheme in (tf.SCHEME_SIGNAL, tf.SCHEME_THREAD):
-        opt = tf.tfft_options(scheme=scheme)
-        assert tf.tfft_plan_create_with(ctypes.byref(h), 1 << 13, 4, 0, ctypes.byref(opt)) == tf.E_UNSUPPORTED
+    # the one-sided scheme is single-pass only
+    opt = tf.tfft_options(scheme=tf.SCHEME_SIGNAL)
+    assert tf.tfft_plan_create_with(ctypes.byref(h), 1 << 13, 4, 0, ctypes.byref(opt)) == tf.E_UNSUPPORTED
     assert not h.value

@@ -168,3 +168,34 @@ def test_thread_scheme_bit_flips(tf):
         y, counts, recs = run(plan, x)
         assert counts["corrected"] == 1, (bit, counts)
         assert oracle.rel_l2(y, oracle.fft(x.astype(np.complex128))) <= TOL["c64"]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("log2n,B", [(13, 6), (16, 3), (20, 2)])
+@pytest.mark.parametrize("inverse", [False, True])
+def test_thread_scheme_multi_pass(tf, dtype, log2n, B, inverse):
+    """Thread-level checks in every pass of a multi-pass plan: parity, no
+    false alarm, and a fault after every stage of every pass corrected in
+    the butterfly that produced it."""
+    n = 1 << log2n
+    x = inputs.uniform(790 + log2n, B, n, NPDT[dtype])
+    ref = oracle.fft(x.astype(np.complex128), inverse=inverse)
+    plan = tf.Plan(n, B, dtype, scheme="thread")
+    info = plan.info()
+    assert info["passes"] >= 2
+    y, counts, recs = run(plan, x, inverse)
+    assert oracle.rel_l2(y, ref) <= TOL[dtype] and counts["detected"] == 0
+    rng = inputs.fault_rng(790 + log2n)
+    for p in range(info["passes"]):
+        M = info["pass_len"][p]
+        rad = info["radices"][p]
+        for stage in range(info["stages"][p]):
+            sig, idx = int(rng.integers(B)), int(rng.integers(n))
+            plan.set_faults([dict(signal=sig, pass_=p, stage=stage, index=idx, value=0.9 + 0.4j)])
+            y, counts, recs = run(plan, x, inverse)
+            assert counts["detected"] == 1 and counts["corrected"] == 1, (p, stage, counts)
+            r = recs[0]
+            q = ((idx % M) // math.prod(rad[:stage])) % rad[stage]
+            assert r.signal == sig and r.pass_ == p and r.method == tf.LOC_THREAD
+            assert abs(r.ratio - (q + 1)) < 1e-3, (p, stage, r.ratio, q)
+            assert oracle.rel_l2(y, ref) <= TOL[dtype], (p, stage)
