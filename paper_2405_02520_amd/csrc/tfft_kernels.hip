@@ -4,9 +4,11 @@
 // workgroup owns one checksum group at a time (Section IV-B.2, the
 // threadblock-level two-sided checksum) and walks its members a tile of C
 // signals at a time:
-//   load   coalesced global loads into registers; in the same registers the
-//          pre-transform checksum c . x (fp64) is accumulated, weighted by 1
-//          and by the member's one-based index (Section III, Eq. (4)-(5));
+//   load   coalesced global loads of the next tile issued while the current
+//          one is transformed (complex64: into registers; complex128: straight
+//          into a second LDS buffer); on the loaded values the pre-transform
+//          checksum c . x (fp64) is accumulated, weighted by 1 and by the
+//          member's one-based index (Section III, Eq. (4)-(5));
 //   stages Stockham radix-E butterflies held in registers (the thread-level
 //          macro FFT, Section IV-A.2) with LDS transposes between stages;
 //          stage twiddles come from an fp64-generated table rounded once;
@@ -16,7 +18,9 @@
 //          recorded with the residual quotient that locates the member.
 // Flagged groups are corrected afterwards by a separate launch (delayed,
 // batched correction, Section III-B) that rebuilds the located member from
-// the transform of the group's combined input, in fp64.
+// the transform of the group's combined input, in fp64.  Template variants
+// give the one-sided (per-signal) and thread-level (per-butterfly) schemes
+// compared in Section V.
 #include <type_traits>
 #include <utility>
 
@@ -806,7 +810,7 @@ pass_kernel(PassArgs a) {
             });
 
             // final values: register m holds output position k = j + T m
-            // inter-pass twiddle (COLS): w_N^{k sub} = A B^m with A = w_N^{j sub},
+            // inter-pass twiddle (strided passes): w_N^{k sub} = A B^m with A = w_N^{j sub},
             // B = w_N^{T sub}, products in fp64, each rounded once
             if constexpr (KIND == KIND_STRIDED) {
                 cx<double> P = twA;
@@ -1066,7 +1070,7 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
         if (rec.pass != a.pass || rec.action != 1) continue;
         const int64_t g = rec.group;
 
-        // applied output twiddle of member loc at output k (1 outside COLS)
+        // applied output twiddle of member loc at output k (1 outside strided passes)
         auto applied = [&](const MemberLoc &L, int k) -> cx<double> {
             if constexpr (KIND == KIND_STRIDED) {
                 cx<double> w = itw(a, (int64_t(k) * L.tw_i * a.tw_scale) % a.n);
