@@ -317,9 +317,8 @@ def bench_ragged(args):
 def bench_schemes(args):
     """Checksum overhead by granularity (the comparison of one-sided,
     thread-level two-sided and threadblock-level two-sided schemes): N =
-    2^8..2^16 (the one-sided scheme up to 2^12), 2^28 (complex64) / 2^27
-    (complex128) elements, FT CORRECT without faults against FT OFF on the
-    same kernels."""
+    2^8..2^16, 2^28 (complex64) / 2^27 (complex128) elements, FT CORRECT
+    without faults against FT OFF on the same kernels."""
     import numpy as np
     import torch
 
@@ -337,7 +336,7 @@ def bench_schemes(args):
             xd = torch.from_numpy(inputs.uniform(inputs.sweep_seed(k, dt == "c128"), B, n, npdt)).cuda()
             out = torch.empty_like(xd)
             ms = {}
-            schemes = ("block", "signal", "thread") if k <= 12 else ("block", "thread")
+            schemes = ("block", "signal", "thread")
             for scheme in schemes:
                 plan = tf.Plan(n, B, dt, scheme=scheme)
                 for mode in (["off"] if scheme == "block" else []) + ["correct"]:
@@ -362,8 +361,8 @@ def bench_schemes(args):
             for s in ("block", "signal", "thread")}
     print(json.dumps({"metric": "checksum overhead % vs FT off, by scheme granularity", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "mean_overhead_pct": mean, "sizes": rows,
-                      "config": {"workload": "forward C2C, N = 2^8..2^16 (one-sided scheme up to 2^12), N*batch = 2^28 (c64) "
-                                             "/ 2^27 (c128), U[-1,1), FT correct without faults"}}), flush=True)
+                      "config": {"workload": "forward C2C, N = 2^8..2^16, N*batch = 2^28 (c64) / 2^27 (c128), U[-1,1), "
+                                             "FT correct without faults"}}), flush=True)
 
 
 def bench_calibrate(args):

@@ -74,17 +74,26 @@ enum tfft_action {
 };
 
 /* Location method of a record.  TFFT_LOC_THREAD: the thread-level scheme
- * found the fault inside one radix butterfly; record.sub then holds that
- * butterfly's stage and the ratio is k + 1 for its wrong output k. */
-enum tfft_locate { TFFT_LOC_NONE = 0, TFFT_LOC_QUOTIENT = 1, TFFT_LOC_PER_SIGNAL = 2, TFFT_LOC_THREAD = 3 };
+ * found the fault inside one radix butterfly; in a one-pass plan record.sub
+ * then holds that butterfly's stage, and the ratio is k + 1 for its wrong
+ * output k.  TFFT_LOC_SUBSIGNAL: the one-sided scheme flagged one sub-signal
+ * of a multi-pass plan's pass (record.sub), recomputed alone. */
+enum tfft_locate {
+    TFFT_LOC_NONE = 0,
+    TFFT_LOC_QUOTIENT = 1,
+    TFFT_LOC_PER_SIGNAL = 2,
+    TFFT_LOC_THREAD = 3,
+    TFFT_LOC_SUBSIGNAL = 4
+};
 
 /* Granularity of the checksum (TurboFFT Sec. IV-B and the overhead
  * comparison of Sec. V).
  *   BLOCK  - two-sided checksum over a group of G signals, one residual pair
  *            per group reduced over the workgroup (the default);
- *   SIGNAL - one-sided: one residual per signal (transform encoding only),
- *            reduced over the signal's threads; a flagged signal is
- *            recomputed in binary64;
+ *   SIGNAL - one-sided: one residual per signal (per sub-signal in the
+ *            passes of multi-pass plans; transform encoding only), reduced
+ *            over its threads; a flagged (sub-)signal is recomputed in
+ *            binary64;
  *   THREAD - two-sided checks of every radix butterfly inside the thread that
  *            computes it (two transform encodings e and (k+1) e locate the
  *            wrong output); a flagged butterfly is recomputed in registers.
@@ -103,7 +112,7 @@ typedef struct {
                         length gives E_UNSUPPORTED */
     int32_t grid_scale; /* 0 = default; else workgroups per launch = default * 2^grid_scale
                            (-3..3), a tuning knob */
-    int32_t scheme;  /* enum tfft_scheme; SIGNAL needs n <= 2^12 (one pass) */
+    int32_t scheme;  /* enum tfft_scheme */
     int32_t reserved[5];
 } tfft_options;
 

@@ -32,7 +32,7 @@ OK, UNCORRECTABLE = 0, 1
 E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_STATE = -1, -2, -3, -4, -5
 INVERSE_UNSCALED = 1
 ACT_DETECTED, ACT_CORRECTED, ACT_BENIGN, ACT_UNCORRECTABLE = 1, 2, 3, 4
-LOC_NONE, LOC_QUOTIENT, LOC_PER_SIGNAL, LOC_THREAD = 0, 1, 2, 3
+LOC_NONE, LOC_QUOTIENT, LOC_PER_SIGNAL, LOC_THREAD, LOC_SUBSIGNAL = 0, 1, 2, 3, 4
 SCHEME_BLOCK, SCHEME_SIGNAL, SCHEME_THREAD = 0, 1, 2
 _SCHEMES = {"block": SCHEME_BLOCK, "signal": SCHEME_SIGNAL, "thread": SCHEME_THREAD}
 ACTION_NAMES = {ACT_DETECTED: "detected", ACT_CORRECTED: "corrected", ACT_BENIGN: "benign",
@@ -158,7 +158,7 @@ class Plan:
     def __init__(self, n: int, batch: int, dtype="c64", group: int = 0, kappa: float = 0.0,
                  inverse_unscaled: bool = False, passes: int = 0, grid_scale: int = 0, scheme="block"):
         """scheme: "block" (two-sided, per group of signals), "signal"
-        (one-sided, per signal; n <= 4096) or "thread" (per radix
+        (one-sided, per signal or sub-signal) or "thread" (per radix
         butterfly)."""
         self.n, self.batch = int(n), int(batch)
         self.dtype_code = _dtype_code(dtype)

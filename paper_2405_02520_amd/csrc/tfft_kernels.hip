@@ -474,7 +474,9 @@ __device__ __forceinline__ void thread_check(cx<R> (&d)[E], const cx<R> (&vin)[E
 // FT_SIGNAL (one-sided: one residual per signal, reduced over the signal's
 // threads; a flagged signal is recomputed) or FT_THREAD (two-sided checks of
 // every radix butterfly inside the thread that computes it, corrected in
-// registers).  FT_SIGNAL exists for single-pass plans.
+// registers).  In one-pass plans FT_SIGNAL makes every signal a group of its
+// own (tiles of C groups); in the passes of multi-pass plans it keeps the
+// tiles of FT_BLOCK and checks every sub-signal of a tile separately.
 template <typename R, int M, int KIND, int FT>
 __global__ void __launch_bounds__(cfg_threads(sizeof(R) == 8, M, KIND))
 pass_kernel(PassArgs a) {
@@ -487,6 +489,8 @@ pass_kernel(PassArgs a) {
     // 26% more bytes than the output holds).
     constexpr bool NT_ST = KIND == KIND_ROWS || cfg_C(FP64, M, KIND) * int(sizeof(cx<R>)) >= TFFT_NT_MIN_ROW;
     constexpr bool ENC = BLK || SIG;  // input and output encodings
+    constexpr bool SIGR = SIG && KIND == KIND_ROWS;  // one-sided, tiles of one-signal groups
+    constexpr bool SIGM = SIG && KIND != KIND_ROWS;  // one-sided, per sub-signal of block tiles
     constexpr int E = cfg_E(FP64, M, KIND);
     constexpr int T = M / E;
     constexpr int C = cfg_C(FP64, M, KIND);
@@ -577,10 +581,10 @@ pass_kernel(PassArgs a) {
     if (nwg % 8 == 0) wl = (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;  // XCD-contiguous group ranges
 
     // FT_SIGNAL: a tile of C signals per iteration, each its own group (G = 1)
-    const int rounds = SIG ? 1 : a.G / C;
-    const int64_t n_iter = SIG ? (a.n_groups + C - 1) / C : a.n_groups;
+    const int rounds = SIGR ? 1 : a.G / C;
+    const int64_t n_iter = SIGR ? (a.n_groups + C - 1) / C : a.n_groups;
     auto mloc = [&](int64_t gg, int rr) -> MemberLoc {
-        if constexpr (SIG) return member_loc<M, KIND, C>(a, gg * C + c, 0);
+        if constexpr (SIGR) return member_loc<M, KIND, C>(a, gg * C + c, 0);
         else return member_loc<M, KIND, C>(a, gg, rr * C + c);
     };
     // Software pipeline: the loads of the next tile (next round, or round 0 of
@@ -655,18 +659,90 @@ pass_kernel(PassArgs a) {
             pend = false;
         }
     };
+    // One-sided check of each member (signal or sub-signal) of a tile: sum
+    // the member's residual and energy over its threads, test it against its
+    // own threshold and record it (method: 1 for a one-signal group, 4 for a
+    // sub-signal of a block tile, which the correction recomputes alone).
+    __shared__ double redm[SIGM && KIND == KIND_STRIDED ? WAVES : 1][SIGM && KIND == KIND_STRIDED ? C : 1][3];
+    auto member_check = [&](int64_t grp, int mem, bool valid, double d1r, double d1i, R ssum, int method) {
+        double v[3] = {d1r, d1i, double(ssum)};
+        bool mine;  // this thread reports the member
+        if constexpr (KIND == KIND_STRIDED) {
+            // threads of member c are the lanes c + C k
+            for (int off = C; off < 64; off <<= 1) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) v[q] += __shfl_xor(v[q], off, 64);
+            }
+            if constexpr (NT > 64) {
+                if ((tid & 63) < C) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) redm[tid >> 6][tid & 63][q] = v[q];
+                }
+                __syncthreads();
+                if (tid < C) {
+                    v[0] = v[1] = v[2] = 0.0;
+                    for (int w = 0; w < WAVES; ++w)
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) v[q] += redm[w][tid][q];
+                }
+            }
+            mine = tid < C;
+        } else {
+            // threads of member c are the T consecutive threads c T + j
+            if constexpr (T <= 64) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) v[q] = wave_sum(v[q], T);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) v[q] = wave_sum_dpp(v[q], Dpp64{});
+                if ((tid & 63) == 63) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) red[tid >> 6][q] = v[q];
+                }
+                __syncthreads();
+                if (j == 0) {
+                    v[0] = v[1] = v[2] = 0.0;
+                    for (int w = c * (T / 64); w < (c + 1) * (T / 64); ++w)
+                        for (int q = 0; q < 3; ++q) v[q] += red[w][q];
+                }
+            }
+            mine = j == 0;
+        }
+        if (mine && valid) {
+            const double tau = a.tau_coef * sqrt(v[2]);
+            if (!(sqrt(v[0] * v[0] + v[1] * v[1]) <= tau)) {
+                const unsigned long long slot = atomicAdd(&a.rep->n_flag, 1ULL);
+                if ((int64_t)slot < a.rec_cap) {
+                    DevRecord rc;
+                    rc.group = grp;
+                    rc.pass = a.pass;
+                    rc.action = 1;  // detected
+                    rc.member = mem;
+                    rc.method = method;
+                    rc.d1r = v[0];
+                    rc.d1i = v[1];
+                    rc.d2r = v[0];  // one weight: the quotient is 1
+                    rc.d2i = v[1];
+                    rc.tau = tau;
+                    rc.s = v[2];
+                    a.recs[slot] = rc;
+                }
+            }
+        }
+        if constexpr (NT > 64) __syncthreads();
+    };
     for (int64_t g = wl; g < n_iter; g += nwg) {
         const int64_t gsig = g * C + c;  // FT_SIGNAL: this thread's signal (= its group)
         // the fault lookup reads a table entry or a constant -1 (no branch)
         const int32_t *fhp;
-        if constexpr (SIG) fhp = (a.fault_head && gsig < a.n_groups) ? a.fault_head + gsig : &kNoFault;
+        if constexpr (SIGR) fhp = (a.fault_head && gsig < a.n_groups) ? a.fault_head + gsig : &kNoFault;
         else fhp = a.fault_head ? a.fault_head + g : &kNoFault;
         const int fh = *fhp;
         // the group's first fault, staged in LDS once (fh is uniform outside
         // FT_SIGNAL, whose threads walk the list themselves)
         __shared__ DevFault f0;
         bool fmulti = true;
-        if constexpr (!SIG) {
+        if constexpr (!SIGR) {
             if (fh >= 0) {
                 __syncthreads();
                 if (tid == 0) f0 = a.faults[fh];
@@ -677,7 +753,7 @@ pass_kernel(PassArgs a) {
         double D1r = 0.0, D1i = 0.0, D2r = 0.0, D2i = 0.0;
         R Ssum = R(0);  // energy of the group's inputs, for the threshold only
         for (int r = 0; r < rounds; ++r) {
-            const int b = SIG ? 0 : r * C + c;
+            const int b = SIGR ? 0 : r * C + c;
             const MemberLoc L = mloc(g, r);
             // offsets inside one signal are below N <= 2^24: 32-bit arithmetic
             cx<R> *dst = out + L.out_off;
@@ -897,51 +973,14 @@ pass_kernel(PassArgs a) {
                     for (int m = 0; m < E; ++m) st_stream<R, NT_ST>(dst + (uint32_t)(j + T * m) * ostr, d[m]);
                 }
             }
+            if constexpr (SIGM) {
+                member_check(g, b, L.valid, D1r, D1i, Ssum, 4);
+                D1r = D1i = 0.0;
+                Ssum = R(0);
+            }
         }  // rounds
 
-        if constexpr (SIG) {
-            // one residual per signal: sum over the T threads of signal c
-            double v[3] = {D1r, D1i, double(Ssum)};
-            if constexpr (T <= 64) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q) v[q] = wave_sum(v[q], T);
-            } else {
-#pragma unroll
-                for (int q = 0; q < 3; ++q) v[q] = wave_sum_dpp(v[q], Dpp64{});
-                if ((tid & 63) == 63) {
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) red[tid >> 6][q] = v[q];
-                }
-                __syncthreads();
-                if (j == 0) {
-                    v[0] = v[1] = v[2] = 0.0;
-                    for (int w = c * (T / 64); w < (c + 1) * (T / 64); ++w)
-                        for (int q = 0; q < 3; ++q) v[q] += red[w][q];
-                }
-            }
-            if (j == 0 && gsig < a.n_groups) {
-                const double tau = a.tau_coef * sqrt(v[2]);
-                if (!(sqrt(v[0] * v[0] + v[1] * v[1]) <= tau)) {
-                    const unsigned long long slot = atomicAdd(&a.rep->n_flag, 1ULL);
-                    if ((int64_t)slot < a.rec_cap) {
-                        DevRecord rc;
-                        rc.group = gsig;
-                        rc.pass = a.pass;
-                        rc.action = 1;  // detected
-                        rc.member = 0;  // the signal itself
-                        rc.method = 1;
-                        rc.d1r = v[0];
-                        rc.d1i = v[1];
-                        rc.d2r = v[0];  // one weight: the quotient is 1
-                        rc.d2i = v[1];
-                        rc.tau = tau;
-                        rc.s = v[2];
-                        a.recs[slot] = rc;
-                    }
-                }
-            }
-            if constexpr (T > 64) __syncthreads();
-        }
+        if constexpr (SIGR) member_check(gsig, 0, gsig < a.n_groups, D1r, D1i, Ssum, 1);
         if constexpr (BLK) {
             // the group's decision from its five sums (one thread)
             auto decide = [&](const double *t) {
@@ -1095,7 +1134,10 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
 
         // location: quotient of the residuals, else per-signal residuals
         int jl = rec.member;
-        int method = jl >= 0 ? 1 : 0;
+        int method = rec.method == 4 ? 4 : (jl >= 0 ? 1 : 0);
+        // a one-sided record (a sub-signal checked alone) is recomputed from
+        // its own input: the sums below then take that member only
+        const int only = rec.method == 4 ? jl : -1;
         if (jl < 0) {
             int ncand = 0, cand = -1;
             for (int b = 0; b < a.G; ++b) {
@@ -1153,7 +1195,7 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
                 for (int u = 0; u < CU; ++u) {
                     const int bm = b0 + u * stride;
                     const MemberLoc Lb = member_loc<M, KIND, C>(a, g, bm < a.G ? bm : 0);
-                    const bool ok = bm < a.G && Lb.valid;
+                    const bool ok = bm < a.G && Lb.valid && (only < 0 || bm == only);
                     v[u] = value(ok ? Lb : L0, bm, n);
                     if (!ok) v[u] = cx<double>{0.0, 0.0};
                 }
@@ -1269,9 +1311,7 @@ static hipError_t launch_kind(int ft, const PassArgs &a, int grid, hipStream_t s
     if (ft == FT_BLOCK) return launch_one<R, M, KIND, FT_BLOCK>(a, grid, st);
     if (ft == FT_NONE) return launch_one<R, M, KIND, FT_NONE>(a, grid, st);
     if (ft == FT_THREAD) return launch_one<R, M, KIND, FT_THREAD>(a, grid, st);
-    if constexpr (KIND == KIND_ROWS) {
-        if (ft == FT_SIGNAL) return launch_one<R, M, KIND, FT_SIGNAL>(a, grid, st);
-    }
+    if (ft == FT_SIGNAL) return launch_one<R, M, KIND, FT_SIGNAL>(a, grid, st);
     return hipErrorInvalidValue;
 }
 

@@ -426,9 +426,7 @@ int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_
     const int scheme = opt ? opt->scheme : TFFT_SCHEME_BLOCK;
     if (force_passes < 0 || force_passes > 3 || grid_scale < -3 || grid_scale > 3) return TFFT_E_INVALID;
     if (scheme < TFFT_SCHEME_BLOCK || scheme > TFFT_SCHEME_THREAD) return TFFT_E_INVALID;
-    // the one-sided scheme exists for single-pass plans; the alternative
-    // schemes are not offered for ragged classes
-    if (scheme == TFFT_SCHEME_SIGNAL && (ilog2_64(n) > 12 || force_passes > 1)) return TFFT_E_UNSUPPORTED;
+    // the alternative schemes are not offered for ragged classes
     if (scheme != TFFT_SCHEME_BLOCK && host_off) return TFFT_E_UNSUPPORTED;
     {
         const int kk = ilog2_64(n);
@@ -499,7 +497,8 @@ int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_
     }
     if (rc == TFFT_OK) {
         int64_t cap = 0;
-        for (int i = 0; i < p->passes; ++i) cap += p->pass[i].n_groups;
+        for (int i = 0; i < p->passes; ++i)  // one-sided multi-pass: one record per sub-signal at most
+            cap += p->pass[i].n_groups * ((p->scheme == TFFT_SCHEME_SIGNAL && p->pass[i].kind != KIND_ROWS) ? p->pass[i].G : 1);
         p->rec_cap = std::max<int64_t>(1, cap);
         if (hipMalloc((void **)&p->d_rep, sizeof(DevReport)) != hipSuccess ||
             hipMalloc((void **)&p->d_recs, sizeof(DevRecord) * (size_t)p->rec_cap) != hipSuccess)
@@ -564,7 +563,8 @@ int tfft_get_report(tfft_plan p, tfft_counts *counts, tfft_record *recs, int64_t
     });
     int64_t groups = 0;
     if (p->last_mode != TFFT_FT_OFF)
-        for (int i = 0; i < p->passes; ++i) groups += p->pass[i].n_groups;
+        for (int i = 0; i < p->passes; ++i)  // one-sided: every (sub-)signal is checked
+            groups += p->pass[i].n_groups * ((p->scheme == TFFT_SCHEME_SIGNAL && p->pass[i].kind != KIND_ROWS) ? p->pass[i].G : 1);
     if (counts) {
         counts->groups_checked = groups;
         counts->detected = (int64_t)h.n_flag;

@@ -136,7 +136,4 @@ def test_scheme_option_validation(tf):
     for scheme in (-1, 3):
         opt = tf.tfft_options(scheme=scheme)
         assert tf.tfft_plan_create_with(ctypes.byref(h), 1024, 4, 0, ctypes.byref(opt)) == tf.E_INVALID
-    # the one-sided scheme is single-pass only
-    opt = tf.tfft_options(scheme=tf.SCHEME_SIGNAL)
-    assert tf.tfft_plan_create_with(ctypes.byref(h), 1 << 13, 4, 0, ctypes.byref(opt)) == tf.E_UNSUPPORTED
     assert not h.value

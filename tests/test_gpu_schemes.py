@@ -199,3 +199,41 @@ def test_thread_scheme_multi_pass(tf, dtype, log2n, B, inverse):
             assert r.signal == sig and r.pass_ == p and r.method == tf.LOC_THREAD
             assert abs(r.ratio - (q + 1)) < 1e-3, (p, stage, r.ratio, q)
             assert oracle.rel_l2(y, ref) <= TOL[dtype], (p, stage)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("log2n,B", [(13, 6), (16, 3), (20, 2)])
+@pytest.mark.parametrize("inverse", [False, True])
+def test_signal_scheme_multi_pass(tf, dtype, log2n, B, inverse):
+    """One-sided checks of every sub-signal in every pass: parity, no false
+    alarm, a fault after every stage of every pass (and on the final values)
+    recomputed, and faults in several sub-signals of one tile all corrected."""
+    n = 1 << log2n
+    x = inputs.uniform(810 + log2n, B, n, NPDT[dtype])
+    ref = oracle.fft(x.astype(np.complex128), inverse=inverse)
+    plan = tf.Plan(n, B, dtype, scheme="signal")
+    info = plan.info()
+    assert info["passes"] >= 2
+    y, counts, recs = run(plan, x, inverse)
+    assert oracle.rel_l2(y, ref) <= TOL[dtype] and counts["detected"] == 0
+    rng = inputs.fault_rng(810 + log2n)
+    for p in range(info["passes"]):
+        M = info["pass_len"][p]
+        done = math.prod(info["pass_len"][: p + 1])
+        for stage in range(-1, info["stages"][p]):
+            sig, idx = int(rng.integers(B)), int(rng.integers(n))
+            mag = math.sqrt(2 * done / 3) / (n if inverse and p == info["passes"] - 1 and stage == -1 else 1)
+            plan.set_faults([dict(signal=sig, pass_=p, stage=stage, index=idx, value=mag * (0.6 - 0.8j))])
+            y, counts, recs = run(plan, x, inverse)
+            assert counts["detected"] == 1 and counts["corrected"] == 1, (p, stage, counts)
+            r = recs[0]
+            assert r.signal == sig and r.pass_ == p and r.method == tf.LOC_SUBSIGNAL
+            assert r.sub == idx // M
+            assert oracle.rel_l2(y, ref) <= TOL[dtype], (p, stage)
+    # adjacent sub-signals of one tile (one group of the block scheme)
+    M0 = info["pass_len"][0]
+    faults = [dict(signal=0, pass_=0, stage=-1, index=i * M0 + 3, value=2.0 - 1.0j) for i in (0, 1, 2)]
+    plan.set_faults(faults)
+    y, counts, recs = run(plan, x, inverse)
+    assert counts["corrected"] == 3 and counts["uncorrectable"] == 0
+    assert oracle.rel_l2(y, ref) <= TOL[dtype]
