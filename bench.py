@@ -64,7 +64,7 @@ def parse():
 
 def cpu_baseline(sizes):
     """The FP64 oracle (C radix-2, OpenMP over signals) on a bounded sample of
-    the same sweep: 2^25 elements of each size."""
+    the same sweep: 2^26 elements of each size."""
     import numpy as np
 
     import oracle
@@ -76,7 +76,7 @@ def cpu_baseline(sizes):
     nsig_total = 0
     for (dt, k) in sizes:
         n = 1 << k
-        b = max(1, (1 << 25) // n)
+        b = max(1, (1 << 26) // n)
         x = inputs.uniform(inputs.sweep_seed(k, dt == "c128"), b, n, np.complex128)
         t0 = time.perf_counter()
         oracle.fft(x)
@@ -84,7 +84,7 @@ def cpu_baseline(sizes):
         flops += 5.0 * n * k * b
         nsig_total += b
     return {"value": flops / t_total / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 recursive radix-2 oracle, {len(sizes)} sizes of the sweep, 2^25 elements per size "
+            "sample": f"FP64 recursive radix-2 oracle, {len(sizes)} sizes of the sweep, 2^26 elements per size "
                       f"(OpenMP over signals), {nsig_total} signals, {t_total:.1f} s",
             "seconds": t_total}
 
