@@ -33,6 +33,12 @@ writes out):
 
 Readings where the paper is silent are listed in the module docstring of
 ``two_sided_group`` and in the design notes.
+
+Parity unpinned: ``threshold`` (the form of tau and the factor kappa).  The
+paper prints no threshold value (its ROC figure is not in the text), so the
+norm-based tau and kappa are readings, calibrated on fault-free runs rather
+than pinned to a value the paper fixes; every detection decision that depends
+on them is tested only with faults far above tau or far below it.
 """
 from __future__ import annotations
 
