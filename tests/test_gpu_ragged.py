@@ -198,9 +198,16 @@ def test_ragged_full_size_sampled(tf):
     y = out.cpu().numpy()
     sample = sorted(set([int(s) for s in sigs if lengths[s] <= 1 << 16]) | set(range(0, 4096, 97)))
     check_signals(x, y, lengths, offsets, dtype, idx=sample)
-    # Parseval per signal: sum |y|^2 = n sum |x|^2
-    seg = torch.repeat_interleave(torch.arange(4096, device="cuda"), torch.from_numpy(lengths).cuda())
-    ex = torch.zeros(4096, dtype=torch.float64, device="cuda").index_add_(0, seg, xd.abs().double() ** 2)
-    ey = torch.zeros(4096, dtype=torch.float64, device="cuda").index_add_(0, seg, out.abs().double() ** 2)
-    ratio = (ey / (ex * torch.from_numpy(lengths).cuda().double())).cpu().numpy()
+    # Parseval per signal: sum |y|^2 = n sum |x|^2.  Energies are summed per
+    # length class over a gathered [count, n] view (no atomics: 5.8e8
+    # elements scattered into 4096 float64 bins contend heavily)
+    def energy(t):
+        e = torch.empty(4096, dtype=torch.float64, device="cuda")
+        for n in np.unique(lengths):
+            sel = np.nonzero(lengths == n)[0]
+            idx = torch.from_numpy(offsets[sel]).cuda()[:, None] + torch.arange(int(n), device="cuda")[None, :]
+            e[torch.from_numpy(sel).cuda()] = (t[idx].abs().double() ** 2).sum(1)
+        return e
+
+    ratio = (energy(out) / (energy(xd) * torch.from_numpy(lengths).cuda().double())).cpu().numpy()
     assert np.all(np.abs(ratio - 1) < 1e-5)
