@@ -273,7 +273,7 @@ struct PassArgs {
     const int64_t *in_sig, *out_sig;
     double kappa_u;     // FT_THREAD: kappa * unit roundoff (butterfly thresholds)
     int32_t fix;        // FT_THREAD: recompute a flagged butterfly (CORRECT mode)
-    int32_t pad_;
+    int32_t m1_log2;    // LAST: log2(m1), so that the row map shifts instead of dividing
 };
 
 // Checksum schemes of a pass kernel (template argument FT).

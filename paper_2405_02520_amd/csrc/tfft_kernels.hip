@@ -201,7 +201,7 @@ __device__ __forceinline__ MemberLoc member_loc(const PassArgs &a, int64_t g, in
             L.out_stride = (uint32_t)a.S;
             L.tw_i = r;
         } else {
-            const int64_t o = (r % a.m1) * a.m2 + r / a.m1;
+            const int64_t o = (r & (a.m1 - 1)) * a.m2 + (r >> a.m1_log2);
             const int64_t beta = L.valid ? u : 0;
             L.in_off = (a.in_sig ? a.in_sig[beta] : u * a.n) + o * M;
             L.out_off = (a.out_sig ? a.out_sig[beta] : u * a.n) + r;
@@ -770,9 +770,10 @@ pass_kernel(PassArgs a) {
             }
             cx<double> twA{1.0, 0.0}, twB{1.0, 0.0};
             if constexpr (KIND == KIND_STRIDED) {
-                // w_L^{k i} = w_N^{k i N/L}
-                twA = itw(a, (int64_t(j) * L.tw_i * a.tw_scale) % a.n);
-                twB = itw(a, (int64_t(T) * L.tw_i * a.tw_scale) % a.n);
+                // w_L^{k i} = w_N^{k i N/L}; N is a power of two, so the
+                // exponent is reduced mod N with a mask
+                twA = itw(a, (int64_t(j) * L.tw_i * a.tw_scale) & (a.n - 1));
+                twB = itw(a, (int64_t(T) * L.tw_i * a.tw_scale) & (a.n - 1));
             }
             if constexpr (LDSPF) {
                 // this tile's DMA (issued one iteration earlier) has landed;
@@ -1112,7 +1113,7 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
         // applied output twiddle of member loc at output k (1 outside strided passes)
         auto applied = [&](const MemberLoc &L, int k) -> cx<double> {
             if constexpr (KIND == KIND_STRIDED) {
-                cx<double> w = itw(a, (int64_t(k) * L.tw_i * a.tw_scale) % a.n);
+                cx<double> w = itw(a, (int64_t(k) * L.tw_i * a.tw_scale) & (a.n - 1));
                 if (a.conj_out) w.im = -w.im;
                 return w;
             } else {

@@ -342,6 +342,7 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
         A.G = P.G;
         A.rb = P.rb;
         A.n_strips = P.n_strips;
+        A.m1_log2 = ilog2_64(P.m1);
         A.n_groups = P.n_groups;
         A.conj_in = inverse ? 1 : 0;
         A.conj_out = inverse ? 1 : 0;
