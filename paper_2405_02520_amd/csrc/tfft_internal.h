@@ -164,6 +164,13 @@ constexpr int cfg_prefetch(int fp64, int M, int kind) { return fp64 ? TFFT_PREFE
 #ifndef TFFT_LDS_RED
 #define TFFT_LDS_RED 0
 #endif
+// The decision of a group taken one group later (1), from partial sums kept
+// in a second LDS slot, so that the group's end needs no barrier of its own
+// (the next group's exchange barriers order the partial sums' writes and
+// reads), or at the group's end between two barriers (0).
+#ifndef TFFT_RED_DEFER
+#define TFFT_RED_DEFER 1
+#endif
 // Deferred stores (see the pass kernel): 0 never, 1 in LDS-prefetching
 // one-pass kernels, 2 in every prefetching kernel (measured: 2-8% slower on
 // the multi-pass sizes, where the kept registers cost more than the wait).

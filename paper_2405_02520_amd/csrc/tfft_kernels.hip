@@ -503,8 +503,14 @@ pass_kernel(PassArgs a) {
     constexpr bool LDS_RED = TFFT_LDS_RED && NT % 64 == 0 && NT > 64 &&
                              C * M * int(sizeof(cx<R>)) >= 5 * NT * int(sizeof(double));
 
+    // block scheme: a group's decision deferred into the next group, which
+    // needs at least one workgroup barrier inside every group
+    constexpr bool RED_DEFER = TFFT_RED_DEFER && BLK && !LDS_RED && NT % 64 == 0 &&
+                               (NSTAGE >= 2 || KIND == KIND_LAST);
+
     __shared__ cx<R> lds[C * M];
     __shared__ double red[WAVES][5];
+    __shared__ double redg[RED_DEFER ? 2 : 1][RED_DEFER ? WAVES : 1][5];
 
     const int tid = threadIdx.x;
     int c, j;
@@ -731,6 +737,43 @@ pass_kernel(PassArgs a) {
         }
         if constexpr (NT > 64) __syncthreads();
     };
+    // a group's decision from its five sums (one thread)
+    auto decide = [&](const double *t, int64_t g) {
+        const double d1r = t[0], d1i = t[1], d2r = t[2], d2i = t[3], S = t[4];
+        const double tau = a.tau_coef * sqrt(S);
+        const double ad1 = sqrt(d1r * d1r + d1i * d1i);
+        if (!(ad1 <= tau)) {
+            const double den = d1r * d1r + d1i * d1i;
+            const double rhor = (d2r * d1r + d2i * d1i) / den;
+            const double rhoi = (d2i * d1r - d2r * d1i) / den;
+            int jl = -1;
+            if (isfinite(rhor) && isfinite(rhoi)) {
+                const double fj = floor(rhor + 0.5);
+                if (fj >= 1.0 && fj <= double(a.G)) {
+                    const double er = rhor - fj;
+                    if (sqrt(er * er + rhoi * rhoi) <= 0.25) jl = int(fj) - 1;
+                }
+            }
+            const unsigned long long slot = atomicAdd(&a.rep->n_flag, 1ULL);
+            if ((int64_t)slot < a.rec_cap) {
+                DevRecord rc;
+                rc.group = g;
+                rc.pass = a.pass;
+                rc.action = 1;  // detected
+                rc.member = jl;
+                rc.method = jl >= 0 ? 1 : 0;
+                rc.d1r = d1r;
+                rc.d1i = d1i;
+                rc.d2r = d2r;
+                rc.d2i = d2i;
+                rc.tau = tau;
+                rc.s = S;
+                a.recs[slot] = rc;
+            }
+        }
+    };
+    int64_t g_prev = -1;  // RED_DEFER: the group whose decision is pending
+    int it = 0;           // RED_DEFER: groups done by this workgroup
     for (int64_t g = wl; g < n_iter; g += nwg) {
         const int64_t gsig = g * C + c;  // FT_SIGNAL: this thread's signal (= its group)
         // the fault lookup reads a table entry or a constant -1 (no branch)
@@ -983,41 +1026,6 @@ pass_kernel(PassArgs a) {
 
         if constexpr (SIGR) member_check(gsig, 0, gsig < a.n_groups, D1r, D1i, Ssum, 1);
         if constexpr (BLK) {
-            // the group's decision from its five sums (one thread)
-            auto decide = [&](const double *t) {
-                const double d1r = t[0], d1i = t[1], d2r = t[2], d2i = t[3], S = t[4];
-                const double tau = a.tau_coef * sqrt(S);
-                const double ad1 = sqrt(d1r * d1r + d1i * d1i);
-                if (!(ad1 <= tau)) {
-                    const double den = d1r * d1r + d1i * d1i;
-                    const double rhor = (d2r * d1r + d2i * d1i) / den;
-                    const double rhoi = (d2i * d1r - d2r * d1i) / den;
-                    int jl = -1;
-                    if (isfinite(rhor) && isfinite(rhoi)) {
-                        const double fj = floor(rhor + 0.5);
-                        if (fj >= 1.0 && fj <= double(a.G)) {
-                            const double er = rhor - fj;
-                            if (sqrt(er * er + rhoi * rhoi) <= 0.25) jl = int(fj) - 1;
-                        }
-                    }
-                    const unsigned long long slot = atomicAdd(&a.rep->n_flag, 1ULL);
-                    if ((int64_t)slot < a.rec_cap) {
-                        DevRecord rc;
-                        rc.group = g;
-                        rc.pass = a.pass;
-                        rc.action = 1;  // detected
-                        rc.member = jl;
-                        rc.method = jl >= 0 ? 1 : 0;
-                        rc.d1r = d1r;
-                        rc.d1i = d1i;
-                        rc.d2r = d2r;
-                        rc.d2i = d2i;
-                        rc.tau = tau;
-                        rc.s = S;
-                        a.recs[slot] = rc;
-                    }
-                }
-            };
             if constexpr (LDS_RED) {
                 // partial sums through the (now idle) exchange buffer, added
                 // up by one wavefront: each thread stores five values instead
@@ -1038,7 +1046,7 @@ pass_kernel(PassArgs a) {
                         for (int w = tid; w < NT; w += 64) v[q] += part[q * NT + w];
                         v[q] = wave_sum_dpp(v[q], Dpp64{});
                     }
-                    if (tid == 63) decide(v);
+                    if (tid == 63) decide(v, g);
                 }
                 __syncthreads();
             } else {
@@ -1051,7 +1059,10 @@ pass_kernel(PassArgs a) {
                     else v[4] = double(wave_sum_dpp(sf, Dpp32{}));
                     if ((tid & 63) == 63) {
 #pragma unroll
-                        for (int q = 0; q < 5; ++q) red[tid >> 6][q] = v[q];
+                        for (int q = 0; q < 5; ++q) {
+                            if constexpr (RED_DEFER) redg[it & 1][tid >> 6][q] = v[q];
+                            else red[tid >> 6][q] = v[q];
+                        }
                     }
                 } else {
                     v[4] = double(Ssum);
@@ -1062,17 +1073,41 @@ pass_kernel(PassArgs a) {
                         for (int q = 0; q < 5; ++q) red[tid >> 6][q] = v[q];
                     }
                 }
-                __syncthreads();
-                if (tid == 0) {
-                    double t[5] = {0, 0, 0, 0, 0};
-                    for (int w = 0; w < WAVES; ++w)
-                        for (int k = 0; k < 5; ++k) t[k] += red[w][k];
-                    decide(t);
+                if constexpr (RED_DEFER) {
+                    // the previous group's sums were written before this
+                    // group's exchange barriers; this group's go to the other
+                    // slot, which is read only after the next group's barriers
+                    if (tid == 0 && g_prev >= 0) {
+                        double t[5] = {0, 0, 0, 0, 0};
+                        for (int w = 0; w < WAVES; ++w)
+                            for (int k = 0; k < 5; ++k) t[k] += redg[(it - 1) & 1][w][k];
+                        decide(t, g_prev);
+                    }
+                    g_prev = g;
+                    ++it;
+                } else {
+                    __syncthreads();
+                    if (tid == 0) {
+                        double t[5] = {0, 0, 0, 0, 0};
+                        for (int w = 0; w < WAVES; ++w)
+                            for (int k = 0; k < 5; ++k) t[k] += red[w][k];
+                        decide(t, g);
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
         }
     }  // groups
+    if constexpr (RED_DEFER) {
+        // the last group's decision
+        __syncthreads();
+        if (tid == 0 && g_prev >= 0) {
+            double t[5] = {0, 0, 0, 0, 0};
+            for (int w = 0; w < WAVES; ++w)
+                for (int k = 0; k < 5; ++k) t[k] += redg[(it - 1) & 1][w][k];
+            decide(t, g_prev);
+        }
+    }
     flush();
 }
 
