@@ -121,6 +121,13 @@ constexpr int cfg_C(int fp64, int M, int kind) {
 #ifndef TFFT_GRID_THREADS
 #define TFFT_GRID_THREADS (4096 * 256)
 #endif
+// Multi-pass kernels of at least this many points per sub-transform get
+// twice that many workgroups (measured: complex64 N = 2^18 and 2^19 7-8%
+// faster, complex128 neutral; the shorter multi-pass tiles lose with it).
+// 0 = off.
+#ifndef TFFT_GRID_MP_BIG_M
+#define TFFT_GRID_MP_BIG_M 512
+#endif
 // Largest log2(N) planned with two passes (three passes above), per element
 // type (measured: complex64 N = 2^20 as 1024 x 1024 has 32-byte tile rows in
 // its first pass and is faster in three).

@@ -205,6 +205,7 @@ int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser, int grid_sca
         tiles = P.n_groups;
     }
     int64_t cap = std::max<int64_t>(8, (int64_t)TFFT_GRID_THREADS / cfg_threads(fp64, M, kind));
+    if (TFFT_GRID_MP_BIG_M > 0 && kind != KIND_ROWS && M >= TFFT_GRID_MP_BIG_M) cap *= 2;
     if (TFFT_GRID_MULT > 0) {
         // a persistent launch: TFFT_GRID_MULT x the workgroups resident at once
         int cus = 0;
