@@ -188,8 +188,9 @@ typedef struct {
 
 /* Create a plan for `batch` transforms of length `n` (a power of two,
  * 2 <= n <= 2^24) of element type `dtype`.  Chooses one pass for n <= 2^12,
- * two passes up to 2^19 (complex64) / 2^20 (complex128) and three above (n = M_1 M_2 [M_3], the tiled FFT of
- * Section IV-A.1, last pass stored transposed); generates every twiddle and
+ * two passes up to 2^19 (complex64) / 2^20 (complex128) and three above
+ * (n = M_1 M_2 [M_3], the tiled FFT of Section IV-A.1, last pass stored
+ * transposed); generates every twiddle and
  * checksum vector in binary64 on the host and rounds it once; allocates the
  * tables, the workspace (multi-pass plans: n * batch elements; three-pass
  * plans also use the output buffer between passes) and the report.
