@@ -199,6 +199,38 @@ def test_multi_pass_faults(tf, dtype, inverse, log2n, B):
             assert oracle.rel_l2(y, ref) <= TOL[dtype], (p, stage)
 
 
+@pytest.mark.parametrize("dtype,log2n,B,group", [("c64", 10, 16384, 16), ("c128", 14, 512, 0)])
+def test_faults_with_many_groups_per_workgroup(tf, dtype, log2n, B, group):
+    """The smallest grid (grid_scale -3) makes every workgroup walk several
+    groups, so a group's decision is taken while the workgroup is in its
+    next group, and the last group's after the loop.  Faults in every
+    group (one pass) or in every eighth signal (two passes, one fault per
+    group): each detected, located and corrected; faulty and sampled
+    signals match the oracle."""
+    n = 1 << log2n
+    x = inputs.uniform(700 + log2n, B, n, NPDT[dtype])
+    plan = tf.Plan(n, B, dtype, group=group, grid_scale=-3)
+    info = plan.info()
+    rng = inputs.fault_rng(700 + log2n)
+    scale = math.sqrt(2 * n / 3)
+    if info["passes"] == 1:
+        G = info["group"][0]
+        sigs = [g * G + int(rng.integers(G)) for g in range(B // G)]
+        faults = [dict(signal=s, pass_=0, stage=-1, index=int(rng.integers(n)),
+                       value=complex(rng.standard_normal(), rng.standard_normal()) * scale) for s in sigs]
+    else:
+        sigs = list(range(0, B, 8))
+        m0 = info["pass_len"][0]
+        faults = [dict(signal=s, pass_=0, stage=-1, index=int(rng.integers(n)),
+                       value=complex(rng.standard_normal(), rng.standard_normal()) * math.sqrt(2 * m0 / 3)) for s in sigs]
+    y, counts, recs, _ = run(tf, x, dtype, faults=faults, plan=plan)
+    assert counts["detected"] == len(faults) and counts["corrected"] == len(faults), counts
+    assert counts["uncorrectable"] == 0
+    assert sorted(r.signal for r in recs) == sorted(sigs)
+    rows = sorted(set(sigs[::4]) | set(range(1, B, 97)))
+    assert oracle.rel_l2(y[rows], reference(x[rows])) <= TOL[dtype]
+
+
 def test_detect_mode_report_matches_oracle(tf):
     """The GPU's d-statistics equal the oracle's on the same outputs."""
     n, G, B = 1024, 16, 64
