@@ -16,7 +16,8 @@
  *  - Status codes are ints (enum tfft_status); nothing throws across the ABI.
  *  - Device buffers are owned by the caller, hold `batch` contiguous signals of
  *    `n` interleaved complex values (re, im) each, row-major [batch][n], and
- *    must be 16-byte aligned.  Input and output must not overlap.
+ *    must be 16-byte aligned.  Input and output are either the same buffer
+ *    (in place; see tfft_exec_forward) or do not overlap at all.
  *  - A plan owns its tables, workspace and report buffers; it is bound to the
  *    device current when it was created and must not be executed on two
  *    streams at once.  hip_stream may be NULL (the null stream).
@@ -142,7 +143,19 @@ typedef struct {
     int64_t dropped;        /* flagged groups beyond the record capacity         */
 } tfft_counts;
 
-/* One flagged group. */
+/* One flagged group.
+ * Checksum groups: in a one-pass plan, group g of G = group[0] members holds
+ * signals g*G .. g*G+G-1 (member b = signal g*G + b; the last group may be
+ * partial).  In pass p of a multi-pass plan (tile C = tile_signals[p],
+ * G = group[p], rb = G / C), the sub-transforms are numbered per signal as
+ * in tfft_fault (sub = o * S_p + i in a strided pass, sub = output row r in
+ * the last pass); an "outer unit" is one block o of one signal (strided
+ * passes, unit = signal * (N / L_p) + o) or one signal (last pass), and a
+ * "strip" is C consecutive sub-transforms i (strided) or rows r (last) of a
+ * unit.  With n_strips = S_p / C (strided) or (N / M_P) / C (last), group g
+ * holds members b = 0..G-1: unit (g / n_strips) * rb + b / C, sub-transform
+ * (g % n_strips) * C + b % C of that unit; members whose unit lies beyond the
+ * batch do not exist (a partial last group). */
 typedef struct {
     int64_t signal;   /* batch index of the affected signal (group's first signal if not located) */
     int64_t sub;      /* multi-pass plans: sub-transform of the located member inside the signal
@@ -203,28 +216,56 @@ int tfft_plan_create_with(tfft_plan *out, int64_t n, int64_t batch, int dtype, c
 int tfft_plan_destroy(tfft_plan p);
 
 /* Forward transform of the plan's batch, d_in -> d_out, on hip_stream.
- * ft_mode is enum tfft_ft_mode.  Resets the report.  Returns E_INVALID for
- * NULL, misaligned or overlapping buffers or a bad mode, E_HIP if a launch
- * fails, else OK (the outcome of the checks is read with tfft_get_report). */
+ * ft_mode is enum tfft_ft_mode.  Resets the report.  d_in == d_out transforms
+ * in place; in CORRECT mode that needs a two-pass plan (the correction of a
+ * pass re-reads that pass's inputs, which in place survive only when they are
+ * in the workspace) or the THREAD scheme, else E_UNSUPPORTED.  Returns
+ * E_INVALID for NULL, misaligned or partially overlapping buffers or a bad
+ * mode, E_HIP if a launch fails, else OK (the outcome of the checks is read
+ * with tfft_get_report). */
 int tfft_exec_forward(tfft_plan p, const void *d_in, void *d_out, int ft_mode, void *hip_stream);
 
 /* Inverse transform (w_N^{-jn}; times 1/N unless TFFT_INVERSE_UNSCALED). */
 int tfft_exec_inverse(tfft_plan p, const void *d_in, void *d_out, int ft_mode, void *hip_stream);
 
 /* Copy out the report of the last execution: counters into *counts (may be
- * NULL) and up to `cap` records, sorted by (pass, group), into recs (may be
- * NULL when cap == 0).  Synchronises the stream of the last execution.
+ * NULL) and up to `cap` records, sorted by (signal, pass, group, sub), into
+ * recs (may be NULL when cap == 0).  Synchronises the stream of the last execution.
  * Returns UNCORRECTABLE if any flagged group was left uncorrected in CORRECT
  * mode, E_STATE before the first execution, else OK. */
 int tfft_get_report(tfft_plan p, tfft_counts *counts, tfft_record *recs, int64_t cap);
 
 /* Test hook: install `n` fault specifications applied by every following
  * execution (n = 0 clears them).  The specs are validated against the plan
- * (signal, pass, stage and index in range) and copied; E_INVALID otherwise. */
+ * (signal, pass, stage and index in range) and copied; E_INVALID otherwise.
+ * Waits for the plan's last execution (its stream) before replacing the
+ * tables it reads. */
 int tfft_set_faults(tfft_plan p, const tfft_fault *specs, int64_t n);
 
 /* Fill *info with the plan's decomposition and sizes. */
 int tfft_plan_info(tfft_plan p, tfft_plan_desc *info);
+
+/* The description tfft_plan_info would give for a plan created with these
+ * arguments, computed on the host without creating the plan (no device call,
+ * no allocation): validation as tfft_plan_create_with (E_INVALID /
+ * E_UNSUPPORTED), the pass decomposition N = M_1..M_P of the tiled FFT
+ * (Section IV-A.1), thread radix, tile and stage radices of every pass, the
+ * checksum groups and the workspace size. */
+int tfft_plan_describe(int64_t n, int64_t batch, int dtype, const tfft_options *opt, tfft_plan_desc *info);
+
+/* Host generators of the tables a plan uploads (no device call):
+ *  tfft_host_root: out[0] + i out[1] = w_n^t = exp(-2 pi i t / n) in binary64,
+ *    for any integer t and n >= 1, the twiddle of the DFT matrix (Section II;
+ *    the paper precomputes twiddles, Section IV-A.3).  The angle is reduced
+ *    exactly in integers to a quadrant and libm sees only [0, pi/4].
+ *  tfft_host_checksum_vector: the precomputed checksum vector
+ *    c = scale * (e^T W)^T with e_k = w_3^k, for a length-m DFT matrix W
+ *    (w_m^{-kn} when inverse != 0), Section II-C Eq. (1)-(2); out[2n],
+ *    out[2n+1] = c_n for n < m (2m doubles, caller-owned).  m a power of two,
+ *    2..2^24.
+ * E_INVALID for a NULL out or an argument outside those ranges. */
+int tfft_host_root(int64_t t, int64_t n, double *out);
+int tfft_host_checksum_vector(int64_t m, int inverse, double scale, double *out);
 
 /* Measurement instrument.  With timing enabled (enable != 0), every
  * execution records HIP events on its stream immediately before and after

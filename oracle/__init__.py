@@ -30,6 +30,9 @@ writes out):
 * ``fourstep`` -- Section IV-A.1 (tiled FFT): a length N1*N2 transform as N2
   column transforms, a twiddle, and N1 row transforms whose outputs are stored
   transposed.  Used to state the per-pass checksum domains of a two-pass plan.
+* ``tiled`` -- the same for P passes (the four-step applied recursively), with
+  the inputs, twiddles and outputs of every pass: the per-pass checksum domains
+  of two- and three-pass plans.
 
 Readings where the paper is silent are listed in the module docstring of
 ``two_sided_group`` and in the design notes.
@@ -484,6 +487,83 @@ def fourstep(x, n1: int, n2: int, inverse: bool = False, scale: float | None = N
     out = fft(np.ascontiguousarray(mid), inverse=inverse, scale=s)  # rows
     y = np.ascontiguousarray(np.transpose(out, (0, 2, 1))).reshape(B, n)
     return dict(mid=np.ascontiguousarray(mid), out=out, y=y, tw=tw)
+
+
+def _mixed_digits(v, radices):
+    """Digits of v in the mixed radix ``radices`` (most significant first)."""
+    out = []
+    for r in reversed(radices):
+        out.append(v % r)
+        v = v // r
+    return list(reversed(out))
+
+
+def tiled(x, lens, inverse: bool = False, scale: float | None = None):
+    """Length N = prod(lens) transform of each row of x as P = len(lens)
+    passes of the tiled FFT (Section IV-A.1): pass p transforms the axis of
+    length lens[p], multiplies by the twiddle between passes and leaves the
+    data in place; the last pass transforms contiguous rows and stores them
+    transposed.  It is the decimation-in-frequency four-step applied
+    recursively: within a block of L = lens[p] * ... * lens[P-1] elements the
+    lens[p] points of axis p lie S = L / lens[p] apart, and
+
+        DFT_L(v)[k + lens[p] k'] = DFT_S( w_L^{i k} DFT_{lens[p]}(v[n S + i])_k )_{k'}
+
+    so after the DFT along the axis and the twiddle w_L^{k i}, each of the
+    lens[p] rows of length S is an independent length-S transform whose output
+    k' belongs at k + lens[p] k' of the block's output.
+
+    Returns dict(passes=[...], y=[B, N]).  passes[p] holds ``inp`` [B, sub, M]
+    (the M inputs of each sub-transform), ``tw`` [sub, M] (the twiddle applied
+    to its outputs; ones in the last pass) and ``out`` [B, sub, M] (its
+    outputs after the twiddle and, in the last pass, the scale).  Sub-transform
+    numbering: in pass p < P-1, sub = o * S + i for block o and offset i
+    inside the stride; in the last pass, sub = r, the output row, whose
+    outputs go to y[r + (N / M) k]."""
+    x = np.asarray(x, dtype=np.complex128)
+    lens = [int(m) for m in lens]
+    B, n = x.shape
+    assert int(np.prod(lens)) == n
+    P = len(lens)
+    s = (1.0 / n if inverse else 1.0) if scale is None else scale
+    a = x.copy()
+    passes = []
+    for p in range(P - 1):
+        M = lens[p]
+        L = int(np.prod(lens[p:]))
+        S = L // M
+        O = n // L
+        inp = np.ascontiguousarray(a.reshape(B, O, M, S).transpose(0, 1, 3, 2)).reshape(B, O * S, M)
+        i = np.arange(S, dtype=np.int64)[:, None]
+        k = np.arange(M, dtype=np.int64)[None, :]
+        tw = omega((i * k) % L, L)
+        if inverse:
+            tw = np.conj(tw)
+        tw = np.tile(tw, (O, 1))                                       # [O * S, M]
+        out = fft(inp, inverse=inverse, scale=1.0) * tw[None]
+        passes.append(dict(inp=inp, tw=tw, out=out))
+        a = np.ascontiguousarray(out.reshape(B, O, S, M).transpose(0, 1, 3, 2)).reshape(B, n)
+    M = lens[-1]
+    rows = n // M
+    # the row at element offset rho * M holds the output digits (k_0, .., k_{P-2})
+    # of the earlier passes, k_0 most significant; the final index of its
+    # output k is k_0 + lens[0] k_1 + ... + (N / M) k
+    head = lens[:-1]
+    r_of_rho = np.zeros(rows, dtype=np.int64)
+    for rho in range(rows):
+        dg = _mixed_digits(rho, head)
+        r, w = 0, 1
+        for d_, m_ in zip(dg, head):
+            r += d_ * w
+            w *= m_
+        r_of_rho[rho] = r
+    src = a.reshape(B, rows, M)
+    inp = np.empty_like(src)
+    inp[:, r_of_rho, :] = src
+    out = fft(inp, inverse=inverse, scale=s)
+    passes.append(dict(inp=inp, tw=np.ones((rows, M), dtype=np.complex128), out=out))
+    y = np.ascontiguousarray(out.transpose(0, 2, 1)).reshape(B, n)
+    return dict(passes=passes, y=y)
 
 
 def rel_l2(a, b) -> float:

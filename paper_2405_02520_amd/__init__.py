@@ -105,6 +105,11 @@ _sig = {
     "tfft_ragged_info": ([_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(tfft_plan_desc), ctypes.c_int64],
                          ctypes.c_int),
+    "tfft_plan_describe": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(tfft_options),
+                            ctypes.POINTER(tfft_plan_desc)], ctypes.c_int),
+    "tfft_host_root": ([ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tfft_host_checksum_vector": ([ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
+                                  ctypes.c_int),
     "tfft_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "tfft_version": ([], ctypes.c_int),
 }
@@ -374,6 +379,36 @@ class Ragged:
         """Merged (counts dict, [Record]) of the last execution; records carry the ragged index."""
         c, out, self.last_status = _report(tfft_ragged_get_report, self._h, cap)
         return c, out
+
+
+def describe(n: int, batch: int, dtype="c64", group: int = 0, kappa: float = 0.0, passes: int = 0,
+             grid_scale: int = 0, scheme="block") -> dict:
+    """The plan description (as ``Plan.info``) of a plan with these
+    arguments, computed on the host without a device."""
+    sch = _SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+    opt = tfft_options(group=int(group), kappa=float(kappa), passes=int(passes), grid_scale=int(grid_scale), scheme=sch)
+    d = tfft_plan_desc()
+    _check(tfft_plan_describe(int(n), int(batch), _dtype_code(dtype), ctypes.byref(opt), ctypes.byref(d)),
+           "tfft_plan_describe")
+    return _desc_dict(d)
+
+
+def host_root(t: int, n: int) -> complex:
+    """w_n^t as the plans generate it (binary64, host)."""
+    out = (ctypes.c_double * 2)()
+    _check(tfft_host_root(int(t), int(n), out), "tfft_host_root")
+    return complex(out[0], out[1])
+
+
+def host_checksum_vector(m: int, inverse: bool = False, scale: float = 1.0):
+    """The checksum vector c = scale (e^T W)^T a plan uploads (binary64,
+    host), as a complex128 numpy array."""
+    import numpy as np
+    out = np.empty(2 * int(m), dtype=np.float64)
+    _check(tfft_host_checksum_vector(int(m), 1 if inverse else 0, float(scale),
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "tfft_host_checksum_vector")
+    return out.view(np.complex128)
 
 
 def _desc_dict(d) -> dict:

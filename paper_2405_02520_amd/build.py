@@ -1,10 +1,12 @@
 """Build the HIP library ``libtfft.so`` in-tree with hipcc for gfx950.
 
-    python paper_2405_02520_amd/build.py [--resource-usage]
+    python paper_2405_02520_amd/build.py [--resource-usage] [-DNAME=VALUE ...] [--out=PATH]
 
-The two translation units are compiled in parallel and linked into a shared
-library next to this file.  Every HIP source is built with packed FP32
-instructions disabled (the compiler still vectorises nothing by hand).
+The kernels are instantiated per (element type, pass length): ``tfft_inst.hip``
+is compiled once for each pair, in parallel with the dispatch unit and the
+host code, and the objects are linked into a shared library next to this
+file.  Every HIP source is built with packed FP32 instructions disabled (the
+compiler still vectorises nothing by hand).
 """
 from __future__ import annotations
 
@@ -23,14 +25,18 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
-SOURCES = ["tfft_kernels.hip", "tfft_plan.cpp"]
+# (source, extra defines, object name)
+LENGTHS = [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
+UNITS = [("tfft_kernels.hip", [], "tfft_kernels"), ("tfft_plan.cpp", [], "tfft_plan")] + [
+    ("tfft_inst.hip", [f"-DTFFT_INST_R={r}", f"-DTFFT_INST_M={m}"], f"tfft_inst_{r}_{m}")
+    for r in ("float", "double") for m in LENGTHS]
 
 
-def _compile(src: str, obj: str, extra: list[str]) -> str:
-    cmd = COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, defs: list[str], obj: str, extra: list[str]) -> str:
+    cmd = COMMON + extra + defs + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-8000:]}")
+        raise RuntimeError(f"hipcc failed for {src} {' '.join(defs)}:\n{r.stderr[-8000:]}")
     return r.stderr
 
 
@@ -42,9 +48,14 @@ def build(resource_usage: bool = False, verbose: bool = False, defines=(), lib: 
     os.makedirs(objdir, exist_ok=True)
     extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
     extra += [f"-D{d}" for d in defines]
-    objs = [os.path.join(objdir, s + ".o") for s in SOURCES]
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        logs = list(ex.map(lambda so: _compile(so[0], so[1], extra), zip(SOURCES, objs)))
+    objs = [os.path.join(objdir, name + ".o") for _, _, name in UNITS]
+    jobs = int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 4
+    # the longest units first
+    order = sorted(range(len(UNITS)), key=lambda i: -max([int(d.split("=")[1]) for d in UNITS[i][1]
+                                                          if d.startswith("-DTFFT_INST_M")] or [8192]))
+    with ThreadPoolExecutor(max_workers=min(jobs, len(UNITS))) as ex:
+        futs = {i: ex.submit(_compile, UNITS[i][0], UNITS[i][1], objs[i], extra) for i in order}
+        logs = [futs[i].result() for i in range(len(UNITS))]
     if resource_usage:
         with open(os.path.join(objdir, "resource_usage.log"), "w") as f:
             f.write("\n".join(logs))

@@ -154,7 +154,9 @@ std::vector<double> checksum_vec(int M, bool inverse, double scale) {
     return out;
 }
 
-int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser, int grid_scale) {
+// Geometry of pass idx (no device call): thread radix, tile, checksum
+// groups, workgroups and the threshold coefficient.
+int shape_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser, int grid_scale) {
     PassPlan &P = p->pass[idx];
     const int fp64 = p->dtype == TFFT_C128;
     P.M = M;
@@ -220,7 +222,15 @@ int build_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser, int grid_sca
     P.grid = (int)std::max<int64_t>(1, grid);
     const double u = fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
     P.tau_coef = p->kappa * u * std::sqrt(std::max(1.0, (double)ilog2_64(M))) * std::sqrt((double)M);
+    return TFFT_OK;
+}
 
+// Tables of pass idx (stage twiddles in the element type and in fp64, the
+// checksum vectors of both directions), generated in fp64 and uploaded.
+int upload_pass(tfft_plan_s *p, int idx) {
+    PassPlan &P = p->pass[idx];
+    const int fp64 = p->dtype == TFFT_C128;
+    const int M = P.M;
     // stage twiddles w_M^t, t < M
     std::vector<double> w64(2 * (size_t)M);
     for (int t = 0; t < M; ++t) {
@@ -300,7 +310,15 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
     const size_t esz = p->dtype == TFFT_C128 ? 16 : 8;
     const size_t bytes = (size_t)p->extent * esz;
     const uintptr_t a = (uintptr_t)d_in, b = (uintptr_t)d_out;
-    if ((a < b ? b - a : a - b) < bytes) return TFFT_E_INVALID;
+    // in place (d_in == d_out) works pass by pass: a tile is read before the
+    // same workgroup writes it.  A correction re-reads the inputs of its pass,
+    // which in place survive only in two-pass plans (in -> workspace -> out);
+    // the thread-level scheme corrects in registers.
+    if (a == b) {
+        if (mode == TFFT_FT_CORRECT && p->passes != 2 && p->scheme != TFFT_SCHEME_THREAD) return TFFT_E_UNSUPPORTED;
+    } else if ((a < b ? b - a : a - b) < bytes) {
+        return TFFT_E_INVALID;  // partial overlap
+    }
     Guard guard(p->device);
     hipStream_t st = (hipStream_t)stream;
     const int fp64 = p->dtype == TFFT_C128;
@@ -407,13 +425,9 @@ const char *tfft_status_string(int s) {
 
 namespace {
 
-// Plan construction shared by dense and ragged plans.  host_off (may be
-// NULL): element offsets of the `batch` signals inside buffers spanning
-// `extent` elements.
-int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_options *opt, const int64_t *host_off,
-                int64_t extent) {
-    if (!out) return TFFT_E_INVALID;
-    *out = nullptr;
+// Validation and geometry of a plan (no device call): *p is filled with the
+// pass decomposition and every pass's shape.
+int shape_plan(tfft_plan_s *p, int64_t n, int64_t batch, int dtype, const tfft_options *opt, bool ragged) {
     if (n < 2 || n > (int64_t(1) << 24) || (n & (n - 1)) != 0) return TFFT_E_INVALID;
     if (batch < 1 || dtype < TFFT_C64 || dtype > TFFT_C128) return TFFT_E_INVALID;
     const size_t esz = dtype == TFFT_C128 ? 16 : 8;
@@ -429,26 +443,16 @@ int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_
     if (force_passes < 0 || force_passes > 3 || grid_scale < -3 || grid_scale > 3) return TFFT_E_INVALID;
     if (scheme < TFFT_SCHEME_BLOCK || scheme > TFFT_SCHEME_THREAD) return TFFT_E_INVALID;
     // the alternative schemes are not offered for ragged classes
-    if (scheme != TFFT_SCHEME_BLOCK && host_off) return TFFT_E_UNSUPPORTED;
-    {
-        const int kk = ilog2_64(n);
-        if ((force_passes == 1 && kk > 12) || (force_passes == 2 && (kk < 8 || kk > 20)) ||
-            (force_passes == 3 && kk < 12))
-            return TFFT_E_UNSUPPORTED;
-    }
-
-    tfft_plan_s *p = new (std::nothrow) tfft_plan_s();
-    if (!p) return TFFT_E_NOMEM;
-    (void)hipGetDevice(&p->device);
+    if (scheme != TFFT_SCHEME_BLOCK && ragged) return TFFT_E_UNSUPPORTED;
+    const int k = ilog2_64(n);
+    if ((force_passes == 1 && k > 12) || (force_passes == 2 && (k < 8 || k > 20)) || (force_passes == 3 && k < 12))
+        return TFFT_E_UNSUPPORTED;
     p->n = n;
     p->batch = batch;
     p->dtype = dtype;
     p->flags = flags;
     p->kappa = (opt && opt->kappa > 0) ? opt->kappa : (dtype == TFFT_C128 ? TFFT_KAPPA64 : TFFT_KAPPA32);
     p->scheme = scheme;
-    p->extent = host_off ? extent : n * batch;
-    const int k = ilog2_64(n);
-    int rc = TFFT_OK;
     // one pass up to 2^12; two passes up to 2^19 (complex64) / 2^20; three
     // passes above, the shortest first (tiles of the strided passes then hold
     // >= 16 adjacent sub-signals, i.e. >= 128-byte segments per row)
@@ -468,12 +472,39 @@ int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_
         p->lens[1] = 1 << b;
         p->lens[2] = 1 << c;
     }
-    for (int i = 0; i < p->passes && rc == TFFT_OK; ++i) {
+    for (int i = 0; i < p->passes; ++i) {
         const int kind = p->passes == 1 ? KIND_ROWS : (i == p->passes - 1 ? KIND_LAST : KIND_STRIDED);
-        rc = build_pass(p, i, p->lens[i], kind, Guser, grid_scale);
+        const int rc = shape_pass(p, i, p->lens[i], kind, Guser, grid_scale);
+        if (rc != TFFT_OK) return rc;
     }
+    p->work_bytes = p->passes > 1 ? (size_t)n * (size_t)batch * esz : 0;
+    int64_t cap = 0;
+    for (int i = 0; i < p->passes; ++i)  // one-sided multi-pass: one record per sub-signal at most
+        cap += p->pass[i].n_groups * ((p->scheme == TFFT_SCHEME_SIGNAL && p->pass[i].kind != KIND_ROWS) ? p->pass[i].G : 1);
+    p->rec_cap = std::max<int64_t>(1, cap);
+    return TFFT_OK;
+}
+
+// Plan construction shared by dense and ragged plans.  host_off (may be
+// NULL): element offsets of the `batch` signals inside buffers spanning
+// `extent` elements.
+int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_options *opt, const int64_t *host_off,
+                int64_t extent) {
+    if (!out) return TFFT_E_INVALID;
+    *out = nullptr;
+    tfft_plan_s *p = new (std::nothrow) tfft_plan_s();
+    if (!p) return TFFT_E_NOMEM;
+    int rc = shape_plan(p, n, batch, dtype, opt, host_off != nullptr);
+    if (rc != TFFT_OK) {
+        delete p;
+        return rc;
+    }
+    (void)hipGetDevice(&p->device);
+    p->extent = host_off ? extent : n * batch;
+    for (int i = 0; i < p->passes && rc == TFFT_OK; ++i) rc = upload_pass(p, i);
     if (rc == TFFT_OK && p->passes > 1) {
         // w_N^t = lo[t mod 2^b] * hi[t >> b]
+        const int k = ilog2_64(n);
         p->itw_bits = (k + 1) / 2;
         const int64_t nlo = int64_t(1) << p->itw_bits, nhi = n >> p->itw_bits;
         std::vector<double> lo(2 * (size_t)nlo), hi(2 * (size_t)nhi);
@@ -489,19 +520,12 @@ int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_
         }
         rc = upload(&p->d_itw_lo, lo);
         if (rc == TFFT_OK) rc = upload(&p->d_itw_hi, hi);
-        if (rc == TFFT_OK) {
-            p->work_bytes = (size_t)n * (size_t)batch * esz;
-            if (hipMalloc(&p->d_work, p->work_bytes) != hipSuccess) {
-                p->d_work = nullptr;
-                rc = TFFT_E_NOMEM;
-            }
+        if (rc == TFFT_OK && hipMalloc(&p->d_work, p->work_bytes) != hipSuccess) {
+            p->d_work = nullptr;
+            rc = TFFT_E_NOMEM;
         }
     }
     if (rc == TFFT_OK) {
-        int64_t cap = 0;
-        for (int i = 0; i < p->passes; ++i)  // one-sided multi-pass: one record per sub-signal at most
-            cap += p->pass[i].n_groups * ((p->scheme == TFFT_SCHEME_SIGNAL && p->pass[i].kind != KIND_ROWS) ? p->pass[i].G : 1);
-        p->rec_cap = std::max<int64_t>(1, cap);
         if (hipMalloc((void **)&p->d_rep, sizeof(DevReport)) != hipSuccess ||
             hipMalloc((void **)&p->d_recs, sizeof(DevRecord) * (size_t)p->rec_cap) != hipSuccess)
             rc = TFFT_E_NOMEM;
@@ -560,9 +584,6 @@ int tfft_get_report(tfft_plan p, tfft_counts *counts, tfft_record *recs, int64_t
     if (nrec > 0 &&
         hipMemcpy(dr.data(), p->d_recs, sizeof(DevRecord) * (size_t)nrec, hipMemcpyDeviceToHost) != hipSuccess)
         return TFFT_E_HIP;
-    std::sort(dr.begin(), dr.end(), [](const DevRecord &x, const DevRecord &y) {
-        return x.pass != y.pass ? x.pass < y.pass : x.group < y.group;
-    });
     int64_t groups = 0;
     if (p->last_mode != TFFT_FT_OFF)
         for (int i = 0; i < p->passes; ++i)  // one-sided: every (sub-)signal is checked
@@ -576,25 +597,31 @@ int tfft_get_report(tfft_plan p, tfft_counts *counts, tfft_record *recs, int64_t
         counts->n_records = nrec;
         counts->dropped = (int64_t)h.n_flag - nrec;
     }
-    for (int64_t i = 0; i < std::min(cap, nrec); ++i) {
+    std::vector<tfft_record> out((size_t)nrec);
+    for (int64_t i = 0; i < nrec; ++i) {
         const DevRecord &d = dr[(size_t)i];
-        const PassPlan &P = p->pass[d.pass];
-        tfft_record &r = recs[i];
-        const int mem = d.member >= 0 ? d.member : 0;
+        tfft_record &r = out[(size_t)i];
+        std::memset(&r, 0, sizeof(r));
+        const bool pass_ok = d.pass >= 0 && d.pass < p->passes;
+        const PassPlan &P = p->pass[pass_ok ? d.pass : 0];
+        // a member outside the group (never written by the kernels) reads as
+        // the group's first signal
+        const int mem = (d.member >= 0 && d.member < P.G) ? d.member : 0;
         if (P.kind == KIND_ROWS) {
             r.signal = d.group * P.G + mem;
             r.sub = d.method == TFFT_LOC_THREAD ? (int64_t)d.s : 0;
         } else {
             const int64_t strip = d.group % P.n_strips, ublk = d.group / P.n_strips;
-            const int64_t u = ublk * P.rb + mem / P.C, i = strip * P.C + mem % P.C;
+            const int64_t u = ublk * P.rb + mem / P.C, i2 = strip * P.C + mem % P.C;
             if (P.kind == KIND_STRIDED) {
                 r.signal = u / P.O;
-                r.sub = (u % P.O) * P.S + i;
+                r.sub = (u % P.O) * P.S + i2;
             } else {
                 r.signal = u;
-                r.sub = i;
+                r.sub = i2;
             }
         }
+        if (r.signal < 0 || r.signal >= p->batch) r.signal = std::min<int64_t>(p->batch - 1, std::max<int64_t>(0, r.signal));
         r.group = d.group;
         r.pass = d.pass;
         r.member = d.member;
@@ -606,6 +633,14 @@ int tfft_get_report(tfft_plan p, tfft_counts *counts, tfft_record *recs, int64_t
         r.ratio_re = (d.d2r * d.d1r + d.d2i * d.d1i) / den;
         r.ratio_im = (d.d2i * d.d1r - d.d2r * d.d1i) / den;
     }
+    // deterministic order whatever the order the device wrote them in
+    std::sort(out.begin(), out.end(), [](const tfft_record &x, const tfft_record &y) {
+        if (x.signal != y.signal) return x.signal < y.signal;
+        if (x.pass != y.pass) return x.pass < y.pass;
+        if (x.group != y.group) return x.group < y.group;
+        return x.sub < y.sub;
+    });
+    for (int64_t i = 0; i < std::min(cap, nrec); ++i) recs[i] = out[(size_t)i];
     const bool bad = h.uncorrectable > 0 || (p->last_mode == TFFT_FT_CORRECT && (int64_t)h.n_flag > nrec);
     return bad ? TFFT_UNCORRECTABLE : TFFT_OK;
 }
@@ -613,7 +648,8 @@ int tfft_get_report(tfft_plan p, tfft_counts *counts, tfft_record *recs, int64_t
 int tfft_set_faults(tfft_plan p, const tfft_fault *specs, int64_t n) {
     if (!p || n < 0 || (n > 0 && !specs)) return TFFT_E_INVALID;
     Guard guard(p->device);
-    if (hipDeviceSynchronize() != hipSuccess) return TFFT_E_HIP;
+    // the fault tables are replaced: wait for the last execution that may read them
+    if (p->executed && hipStreamSynchronize(p->last_stream) != hipSuccess) return TFFT_E_HIP;
     clear_faults(p);
     if (n == 0) return TFFT_OK;
     std::vector<std::vector<DevFault>> per(p->passes);
@@ -746,6 +782,7 @@ struct tfft_ragged_s {
     hipStream_t aux[TFFT_GRAPH_BRANCHES] = {};
     hipEvent_t ev_fork = nullptr, ev_join[TFFT_GRAPH_BRANCHES] = {};
     std::vector<int> branch_of;  // class -> branch
+    std::vector<std::vector<tfft_fault>> class_faults;  // installed faults per class (class-local signals)
 };
 
 namespace {
@@ -952,7 +989,7 @@ int tfft_ragged_get_report(tfft_ragged r, tfft_counts *counts, tfft_record *recs
     tfft_counts total;
     std::memset(&total, 0, sizeof(total));
     int status = TFFT_OK;
-    int64_t filled = 0;
+    std::vector<tfft_record> all;
     for (auto &C : r->classes) {
         tfft_counts c;
         int rc = tfft_get_report(C.plan, &c, nullptr, 0);
@@ -969,11 +1006,17 @@ int tfft_ragged_get_report(tfft_ragged r, tfft_counts *counts, tfft_record *recs
         total.n_records += c.n_records;
         total.dropped += c.dropped;
         for (auto &x : v) {
-            if (filled >= cap) break;
             x.signal = C.members[(size_t)x.signal];
-            recs[filled++] = x;
+            all.push_back(x);
         }
     }
+    std::sort(all.begin(), all.end(), [](const tfft_record &x, const tfft_record &y) {
+        if (x.signal != y.signal) return x.signal < y.signal;
+        if (x.pass != y.pass) return x.pass < y.pass;
+        if (x.group != y.group) return x.group < y.group;
+        return x.sub < y.sub;
+    });
+    for (int64_t i = 0; i < std::min<int64_t>(cap, (int64_t)all.size()); ++i) recs[i] = all[(size_t)i];
     if (counts) *counts = total;
     return status;
 }
@@ -993,6 +1036,7 @@ int tfft_ragged_set_faults(tfft_ragged r, const tfft_fault *specs, int64_t n) {
         const int rc = tfft_set_faults(r->classes[c].plan, per[c].data(), (int64_t)per[c].size());
         if (rc != TFFT_OK) return rc;
     }
+    r->class_faults = std::move(per);
     return TFFT_OK;
 }
 
@@ -1037,6 +1081,9 @@ int tfft_ragged_tune(tfft_ragged r, const void *d_in, void *d_out, void *hip_str
             }
         }
         status = build_class(r, ci, best_opt);
+        // the new plan gets the faults installed on the old one
+        if (status == TFFT_OK && ci < r->class_faults.size() && !r->class_faults[ci].empty())
+            status = tfft_set_faults(C.plan, r->class_faults[ci].data(), (int64_t)r->class_faults[ci].size());
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1052,6 +1099,31 @@ int tfft_ragged_info(tfft_ragged r, int64_t *classes, int64_t *lengths, int64_t 
         if (counts) counts[c] = (int64_t)r->classes[(size_t)c].members.size();
         if (descs) tfft_plan_info(r->classes[(size_t)c].plan, &descs[c]);
     }
+    return TFFT_OK;
+}
+
+int tfft_plan_describe(int64_t n, int64_t batch, int dtype, const tfft_options *opt, tfft_plan_desc *info) {
+    if (!info) return TFFT_E_INVALID;
+    tfft_plan_s *p = new (std::nothrow) tfft_plan_s();
+    if (!p) return TFFT_E_NOMEM;
+    int rc = shape_plan(p, n, batch, dtype, opt, false);
+    if (rc == TFFT_OK) rc = tfft_plan_info(p, info);
+    delete p;  // owns no device memory
+    return rc;
+}
+
+int tfft_host_root(int64_t t, int64_t n, double *out) {
+    if (!out || n < 1) return TFFT_E_INVALID;
+    const cd w = unit_root(t, n);
+    out[0] = w.real();
+    out[1] = w.imag();
+    return TFFT_OK;
+}
+
+int tfft_host_checksum_vector(int64_t m, int inverse, double scale, double *out) {
+    if (!out || m < 2 || m > (int64_t(1) << 24) || (m & (m - 1)) != 0 || !std::isfinite(scale)) return TFFT_E_INVALID;
+    const std::vector<double> c = checksum_vec((int)m, inverse != 0, scale);
+    std::memcpy(out, c.data(), sizeof(double) * c.size());
     return TFFT_OK;
 }
 

@@ -244,8 +244,8 @@ def test_detect_mode_report_matches_oracle(tf):
     for g, o in zip(recs, orecs):
         assert g.member == o.located
         assert abs(g.residual - abs(o.d1)) <= 1e-6 * abs(o.d1)
-        # the energy S that scales tau is summed in the element precision
-        assert abs(g.threshold - o.tau) <= 1e-5 * o.tau
+        # the energy S that scales tau is summed in binary64 on both sides
+        assert abs(g.threshold - o.tau) <= 1e-12 * o.tau
         assert abs(g.ratio - o.rho) <= 1e-6 * abs(o.rho)
     # outputs of DETECT mode are the faulty ones; the oracle corrects them
     fixed, _ = oracle.two_sided_batch(x, y, G, kappa=16.0, u=2.0 ** -24)
@@ -291,7 +291,7 @@ def test_exec_validation(tf):
     y = torch.zeros(8, 256, dtype=torch.complex64, device="cuda")
     with pytest.raises(ValueError):
         p.forward(x.to(torch.complex128))
-    with pytest.raises(tf.TfftError):  # in place is rejected
+    with pytest.raises(tf.TfftError):  # in place, one pass, CORRECT: the inputs would be gone
         p.forward(x, out=x)
     # rejected before any launch: misaligned pointer, unknown mode
     assert tf.tfft_exec_forward(p.handle, x.data_ptr() + 8, y.data_ptr(), 0, None) == tf.E_INVALID

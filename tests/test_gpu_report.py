@@ -1,0 +1,192 @@
+"""GPU report parity and boundary behaviour, through the C ABI.
+
+* Per-pass report parity of multi-pass plans: a fault injected on a final
+  value of pass p of a 2- or 3-pass plan (DETECT mode) is reported in that
+  pass with the residual, threshold and quotient the oracle computes for the
+  same checksum group on its own per-pass intermediates (``oracle.tiled``, the
+  tiled FFT of Section IV-A.1 with the inter-pass twiddle absorbed into the
+  output encoding, and ``oracle.two_sided_group``, Section III).
+* A partial last group: a residual quotient that points at a member beyond
+  the batch is not accepted (no write outside the batch).
+* In-place execution where the pass structure allows it.
+* Records are sorted by signal.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import tfft_inputs as inputs
+
+pytestmark = pytest.mark.gpu
+
+NPDT = {"c64": np.complex64, "c128": np.complex128}
+UNIT = {"c64": 2.0 ** -24, "c128": 2.0 ** -53}
+TOL = {"c64": 1e-5, "c128": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def tf():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_02520_amd
+
+    return paper_2405_02520_amd
+
+
+def to_dev(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def group_members(info, p, n, batch, g):
+    """(signal, sub) of the members of checksum group g of pass p, in member
+    order, from the group layout documented with tfft_record."""
+    lens = info["pass_len"]
+    P = info["passes"]
+    M = lens[p]
+    C, G = info["tile_signals"][p], info["group"][p]
+    rb = G // C
+    if p < P - 1:
+        L = math.prod(lens[p:])
+        S, O = L // M, n // L
+        per_unit, n_outer = S, batch * O
+    else:
+        O = 1
+        per_unit, n_outer = n // M, batch
+    n_strips = per_unit // C
+    out = []
+    for b in range(G):
+        u = (g // n_strips) * rb + b // C
+        i = (g % n_strips) * C + b % C
+        if u >= n_outer:
+            break
+        sig, o = divmod(u, O)
+        out.append((sig, o * S + i if p < P - 1 else i))
+    return out
+
+
+CASES = [("c64", 14, 16, 2), ("c128", 14, 8, 2), ("c64", 16, 4, 2), ("c128", 16, 4, 2),
+         ("c64", 18, 2, 3), ("c128", 18, 2, 3)]
+
+
+@pytest.mark.parametrize("dtype,log2n,B,passes", CASES)
+def test_per_pass_report_matches_oracle(tf, dtype, log2n, B, passes):
+    n = 1 << log2n
+    x = inputs.uniform(9100 + log2n + (100 if dtype == "c128" else 0), B, n, NPDT[dtype])
+    plan = tf.Plan(n, B, dtype, passes=passes)
+    info = plan.info()
+    assert info["passes"] == passes
+    lens = info["pass_len"]
+    ref = oracle.tiled(x.astype(np.complex128), lens)
+    rng = inputs.fault_rng(9100 + log2n)
+    xd = to_dev(x)
+    for p in range(passes):
+        M = lens[p]
+        nsub = n // M
+        sig, sub, pos = int(rng.integers(B)), int(rng.integers(nsub)), int(rng.integers(M))
+        # well above the binary32 rounding noise of the group's checksum
+        rms = math.sqrt(2.0 * math.prod(lens[: p + 1]) / 3.0)
+        eps = (64.0 if dtype == "c64" else 1.0) * rms * complex(0.6, -0.8)
+        plan.set_faults([dict(signal=sig, pass_=p, stage=-1, index=sub * M + pos, value=eps)])
+        plan.forward(xd, ft_mode="detect")
+        counts, recs = plan.report()
+        assert counts["detected"] == 1 and len(recs) == 1, (p, counts, recs)
+        r = recs[0]
+        assert (r.pass_, r.signal, r.sub) == (p, sig, sub)
+        mem = group_members(info, p, n, B, r.group)
+        assert mem[r.member] == (sig, sub)
+        ps = ref["passes"][p]
+        X = np.array([ps["inp"][s, q] for s, q in mem])
+        Y = np.array([ps["out"][s, q] for s, q in mem])
+        Y[r.member, pos] += eps
+        TW = np.array([ps["tw"][q] for _, q in mem])
+        _, o = oracle.two_sided_group(X, Y, out_twiddle=TW, kappa=info["kappa"], u=UNIT[dtype], mode="detect")
+        assert o.flagged and o.located == r.member
+        assert abs(r.residual - abs(o.d1)) <= 1e-6 * abs(o.d1), (p, r.residual, abs(o.d1))
+        # pass 0 reads the caller's data: the same energy to rounding order
+        tol_tau = 1e-12 if (p == 0 or dtype == "c128") else 1e-6
+        assert abs(r.threshold - o.tau) <= tol_tau * o.tau, (p, r.threshold, o.tau)
+        assert abs(r.ratio - o.rho) <= 1e-6 * abs(o.rho), (p, r.ratio, o.rho)
+    plan.set_faults([])
+
+
+def test_partial_group_quotient_beyond_the_batch(tf):
+    """Group 1 of a batch of 26 (G = 16) has 10 members.  Two faults at the
+    same output position of members 0 and 1, eps1 = -12/11 eps0, give the
+    quotient d2/d1 = 13: member 12, which does not exist.  It must not be
+    located (the group is uncorrectable), and nothing beyond the batch is
+    written."""
+    import torch
+
+    n, G, B, guard = 256, 16, 26, 16
+    x = inputs.uniform(9300, B + guard, n, np.complex64)
+    sentinel = np.full((B + guard, n), 3.0 - 2.0j, np.complex64)
+    xd, yd = to_dev(x), to_dev(sentinel)
+    plan = tf.Plan(n, B, "c64", group=G)
+    s = math.sqrt(2.0 * n / 3.0)
+    k = 77
+    plan.set_faults([dict(signal=16, pass_=0, stage=-1, index=k, value=11.0 * s),
+                     dict(signal=17, pass_=0, stage=-1, index=k, value=-12.0 * s)])
+    st = torch.cuda.current_stream()
+    assert tf.tfft_exec_forward(plan.handle, xd.data_ptr(), yd.data_ptr(), tf.FT_CORRECT, st.cuda_stream) == tf.OK
+    with pytest.warns(RuntimeWarning):
+        counts, recs = plan.report()
+    assert counts["detected"] == 1 and counts["uncorrectable"] == 1 and counts["corrected"] == 0, (counts, recs)
+    assert abs(recs[0].ratio - 13.0) < 1e-3 and recs[0].member == -1
+    y = yd.cpu().numpy()
+    assert np.all(y[B:] == sentinel[B:]), "written beyond the batch"
+    ref = oracle.fft(x[:16].astype(np.complex128))
+    assert oracle.rel_l2(y[:16], ref) <= 1e-5  # the full group 0 is untouched by the faults
+
+
+@pytest.mark.parametrize("dtype,log2n,B,mode", [("c64", 10, 40, "off"), ("c128", 12, 9, "detect"),
+                                                ("c64", 16, 4, "correct"), ("c128", 15, 3, "correct"),
+                                                ("c64", 21, 1, "off")])
+def test_in_place(tf, dtype, log2n, B, mode):
+    n = 1 << log2n
+    x = inputs.uniform(9400 + log2n, B, n, NPDT[dtype])
+    plan = tf.Plan(n, B, dtype)
+    faults = []
+    if mode == "correct":
+        assert plan.info()["passes"] == 2
+        m0 = plan.info()["pass_len"][0]
+        faults = [dict(signal=B - 1, pass_=0, stage=-1, index=n // 3, value=math.sqrt(2 * m0 / 3) * (1 + 1j)),
+                  dict(signal=0, pass_=1, stage=0, index=n // 5, value=math.sqrt(2 * n / 3) * (1 - 1j))]
+        plan.set_faults(faults)
+    xd = to_dev(x)
+    y = plan.forward(xd, out=xd, ft_mode=mode).cpu().numpy()
+    counts, recs = plan.report()
+    assert oracle.rel_l2(y, oracle.fft(x.astype(np.complex128))) <= TOL[dtype]
+    if mode == "correct":
+        assert counts["corrected"] == 2 and counts["detected"] == 2, (counts, recs)
+    else:
+        assert counts["detected"] == 0
+
+
+def test_in_place_correct_one_pass_is_unsupported(tf):
+    import torch
+
+    plan = tf.Plan(1024, 8, "c64")
+    x = torch.zeros(8, 1024, dtype=torch.complex64, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    assert tf.tfft_exec_forward(plan.handle, x.data_ptr(), x.data_ptr(), tf.FT_CORRECT, st) == tf.E_UNSUPPORTED
+    assert tf.tfft_exec_forward(plan.handle, x.data_ptr(), x.data_ptr(), tf.FT_DETECT, st) == tf.OK
+    # partial overlap stays invalid
+    assert tf.tfft_exec_forward(plan.handle, x.data_ptr(), x.data_ptr() + 8 * 64, tf.FT_OFF, st) == tf.E_INVALID
+
+
+def test_records_sorted_by_signal(tf):
+    n, G, B = 512, 16, 128
+    x = inputs.uniform(9500, B, n, np.complex64)
+    sigs = [117, 3, 64, 40, 99, 22]  # one per group, given out of order
+    plan = tf.Plan(n, B, "c64", group=G)
+    plan.set_faults([dict(signal=s, pass_=0, stage=-1, index=(7 * s) % n, value=5.0) for s in sigs])
+    plan.forward(to_dev(x))
+    counts, recs = plan.report()
+    assert counts["corrected"] == len(sigs)
+    assert [r.signal for r in recs] == sorted(sigs)
