@@ -114,7 +114,11 @@ typedef struct {
     int32_t grid_scale; /* 0 = default; else workgroups per launch = default * 2^grid_scale
                            (-3..3), a tuning knob */
     int32_t scheme;  /* enum tfft_scheme */
-    int32_t reserved[5];
+    int32_t chunk;   /* multi-pass plans: run the batch in chunks of this many signals (a
+                        multiple of 64), each chunk's passes through one workspace slot of
+                        chunk * n elements; 0 = the whole batch at once.  Faults, records
+                        and group numbers are those of the whole batch. */
+    int32_t reserved[4];
 } tfft_options;
 
 /* Description of a plan (tfft_plan_info). */

@@ -43,7 +43,7 @@ _MODES = {"off": FT_OFF, "detect": FT_DETECT, "correct": FT_CORRECT}
 class tfft_options(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("group", ctypes.c_int32), ("kappa", ctypes.c_double),
                 ("passes", ctypes.c_int32), ("grid_scale", ctypes.c_int32), ("scheme", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 MAX_PASSES = 3
@@ -161,15 +161,17 @@ class Plan:
     """A plan for ``batch`` length-``n`` complex transforms on the current device."""
 
     def __init__(self, n: int, batch: int, dtype="c64", group: int = 0, kappa: float = 0.0,
-                 inverse_unscaled: bool = False, passes: int = 0, grid_scale: int = 0, scheme="block"):
+                 inverse_unscaled: bool = False, passes: int = 0, grid_scale: int = 0, scheme="block",
+                 chunk: int = 0):
         """scheme: "block" (two-sided, per group of signals), "signal"
         (one-sided, per signal or sub-signal) or "thread" (per radix
-        butterfly)."""
+        butterfly).  chunk: multi-pass plans run the batch in chunks of this
+        many signals (a multiple of 64; 0 = the whole batch)."""
         self.n, self.batch = int(n), int(batch)
         self.dtype_code = _dtype_code(dtype)
         sch = _SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         opt = tfft_options(flags=INVERSE_UNSCALED if inverse_unscaled else 0, group=int(group), kappa=float(kappa),
-                           passes=int(passes), grid_scale=int(grid_scale), scheme=sch)
+                           passes=int(passes), grid_scale=int(grid_scale), scheme=sch, chunk=int(chunk))
         h = _P()
         _check(tfft_plan_create_with(ctypes.byref(h), self.n, self.batch, self.dtype_code, ctypes.byref(opt)),
                "tfft_plan_create_with")

@@ -47,9 +47,25 @@ constexpr int ipowc(int b, int e) { return e == 0 ? 1 : b * ipowc(b, e - 1); }
 #ifndef TFFT_E32_MP_BIG_MIN
 #define TFFT_E32_MP_BIG_MIN 512
 #endif
+// Occupancy floor of the pass kernels (waves per SIMD the compiler must
+// allow, which caps the registers per thread); 0 = the compiler's choice.
+#ifndef TFFT_WAVES_PER_EU
+#define TFFT_WAVES_PER_EU 0
+#endif
+// One-pass tiles of at least TFFT_E_ROWS_BIG_MIN points use a thread radix
+// of TFFT_E_ROWS_BIG (fewer, larger threads: 512 threads of 16 points for 8192
+// points keep 256 VGPRs per thread where 1024 threads of 8 would spill).
+#ifndef TFFT_E_ROWS_BIG
+#define TFFT_E_ROWS_BIG 16
+#endif
+#ifndef TFFT_E_ROWS_BIG_MIN
+#define TFFT_E_ROWS_BIG_MIN 8192
+#endif
 constexpr int cfg_E(int fp64, int M, int kind) {
-    const int e = fp64 ? (M >= TFFT_E64_BIG_MIN ? TFFT_E64_BIG : TFFT_E64)
-                       : ((kind != KIND_ROWS && M >= TFFT_E32_MP_BIG_MIN) ? TFFT_E32_MP_BIG : TFFT_E32);
+    const int e = (kind == KIND_ROWS && M >= TFFT_E_ROWS_BIG_MIN)
+                      ? TFFT_E_ROWS_BIG
+                      : fp64 ? (M >= TFFT_E64_BIG_MIN ? TFFT_E64_BIG : TFFT_E64)
+                             : ((kind != KIND_ROWS && M >= TFFT_E32_MP_BIG_MIN) ? TFFT_E32_MP_BIG : TFFT_E32);
     return M >= e ? e : M;
 }
 // Threads of a multi-pass tile (a 512-thread workgroup caps a wavefront at
@@ -152,10 +168,28 @@ constexpr int cfg_C(int fp64, int M, int kind) {
 #ifndef TFFT_GRAPH_BRANCHES
 #define TFFT_GRAPH_BRANCHES 4
 #endif
-constexpr int cfg_twreg(int fp64, int M, int kind) { return fp64 ? TFFT_TWREG64 : TFFT_TWREG32; }
-constexpr int cfg_creg(int fp64, int M, int kind) { return fp64 ? TFFT_CREG64 : TFFT_CREG32; }
-// Issue the next tile's loads before transforming the current one.
-constexpr int cfg_prefetch(int fp64, int M, int kind) { return fp64 ? TFFT_PREFETCH64 : TFFT_PREFETCH32; }
+// One-pass plans up to 2^TFFT_ONE_PASS_MAX_LOG2 points (the tile of one
+// signal: 64 KiB complex64, 128 KiB complex128 of LDS).
+#ifndef TFFT_ONE_PASS_MAX_LOG2
+#define TFFT_ONE_PASS_MAX_LOG2 12
+#endif
+// Lengths from which a thread keeps no stage twiddles and no checksum vector
+// in registers (1024-thread one-pass tiles: 128 VGPRs per thread); their
+// stage twiddles come from the LDS octant table.
+#ifndef TFFT_BIG_ROWS_M
+#define TFFT_BIG_ROWS_M 8192
+#endif
+constexpr int cfg_twreg(int fp64, int M, int kind) { return M >= TFFT_BIG_ROWS_M ? 0 : (fp64 ? TFFT_TWREG64 : TFFT_TWREG32); }
+constexpr int cfg_creg(int fp64, int M, int kind) { return M >= TFFT_BIG_ROWS_M ? 0 : (fp64 ? TFFT_CREG64 : TFFT_CREG32); }
+constexpr int cfg_twlds(int fp64, int M, int kind) { return TFFT_TWLDS || M >= TFFT_BIG_ROWS_M; }
+// Issue the next tile's loads before transforming the current one (the
+// complex128 tiles that cannot double-buffer in LDS prefetch into registers).
+#ifndef TFFT_PREFETCH64_BIG
+#define TFFT_PREFETCH64_BIG 1
+#endif
+constexpr int cfg_prefetch(int fp64, int M, int kind) {
+    return fp64 ? (TFFT_PREFETCH64 || (TFFT_PREFETCH64_BIG && M >= TFFT_BIG_ROWS_M)) : TFFT_PREFETCH32;
+}
 // Correction launch: at most TFFT_CORRECT_GRID workgroups (one per record,
 // the rest exit at once), each summing group members TFFT_CORRECT_BATCH at a
 // time.
@@ -288,6 +322,8 @@ struct PassArgs {
     double kappa_u;     // FT_THREAD: kappa * unit roundoff (butterfly thresholds)
     int32_t fix;        // FT_THREAD: recompute a flagged butterfly (CORRECT mode)
     int32_t m1_log2;    // LAST: log2(m1), so that the row map shifts instead of dividing
+    int64_t g_base;     // index of this launch's first group within the pass (a chunk of the
+                        // batch): fault lookup and records use g_base + g
 };
 
 // Checksum schemes of a pass kernel (template argument FT).

@@ -485,7 +485,7 @@ __device__ __forceinline__ void thread_check(cx<R> (&d)[E], const cx<R> (&vin)[E
         const unsigned long long slot = atomicAdd(&a.rep->n_flag, 1ULL);
         if ((int64_t)slot < a.rec_cap) {
             DevRecord rc;
-            rc.group = g;
+            rc.group = a.g_base + g;
             rc.pass = a.pass;
             rc.action = a.fix ? 2 : 1;  // corrected in registers, or detected
             rc.member = b;
@@ -511,8 +511,13 @@ __device__ __forceinline__ void thread_check(cx<R> (&d)[E], const cx<R> (&vin)[E
 // registers).  In one-pass plans FT_SIGNAL makes every signal a group of its
 // own (tiles of C groups); in the passes of multi-pass plans it keeps the
 // tiles of FT_BLOCK and checks every sub-signal of a tile separately.
+#if TFFT_WAVES_PER_EU > 0
+#define TFFT_PASS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(TFFT_WAVES_PER_EU)))
+#else
+#define TFFT_PASS_OCCUPANCY
+#endif
 template <typename R, int M, int KIND, int FT>
-__global__ void __launch_bounds__(cfg_threads(sizeof(R) == 8, M, KIND))
+__global__ void __launch_bounds__(cfg_threads(sizeof(R) == 8, M, KIND)) TFFT_PASS_OCCUPANCY
 pass_kernel(PassArgs a) {
     constexpr int FP64 = sizeof(R) == 8;
     constexpr bool BLK = FT == FT_BLOCK, SIG = FT == FT_SIGNAL, THR = FT == FT_THREAD;
@@ -571,7 +576,7 @@ pass_kernel(PassArgs a) {
     // first octant, w_M^t for t <= M/8, and the exact symmetries of the
     // table (the host builds it from the same octant): no global load in the
     // transform, whose wait would also wait for the prefetch.
-    constexpr bool TWLDS = !TWREG && (cfg_ldspf(FP64, M, KIND) != 0 || TFFT_TWLDS) && M >= 8;
+    constexpr bool TWLDS = !TWREG && (cfg_ldspf(FP64, M, KIND) != 0 || cfg_twlds(FP64, M, KIND)) && M >= 8;
     __shared__ cx<R> twl[TWLDS ? M / 8 + 1 : 1];
     if constexpr (TWLDS) {
         for (int t = tid; t <= M / 8; t += NT) twl[t] = ldg(stw + t);
@@ -754,7 +759,7 @@ pass_kernel(PassArgs a) {
                 const unsigned long long slot = atomicAdd(&a.rep->n_flag, 1ULL);
                 if ((int64_t)slot < a.rec_cap) {
                     DevRecord rc;
-                    rc.group = grp;
+                    rc.group = a.g_base + grp;
                     rc.pass = a.pass;
                     rc.action = 1;  // detected
                     rc.member = mem;
@@ -792,7 +797,7 @@ pass_kernel(PassArgs a) {
             const unsigned long long slot = atomicAdd(&a.rep->n_flag, 1ULL);
             if ((int64_t)slot < a.rec_cap) {
                 DevRecord rc;
-                rc.group = g;
+                rc.group = a.g_base + g;
                 rc.pass = a.pass;
                 rc.action = 1;  // detected
                 rc.member = jl;
@@ -813,8 +818,8 @@ pass_kernel(PassArgs a) {
         const int64_t gsig = g * C + c;  // FT_SIGNAL: this thread's signal (= its group)
         // the fault lookup reads a table entry or a constant -1 (no branch)
         const int32_t *fhp;
-        if constexpr (SIGR) fhp = (a.fault_head && gsig < a.n_groups) ? a.fault_head + gsig : &kNoFault;
-        else fhp = a.fault_head ? a.fault_head + g : &kNoFault;
+        if constexpr (SIGR) fhp = (a.fault_head && gsig < a.n_groups) ? a.fault_head + a.g_base + gsig : &kNoFault;
+        else fhp = a.fault_head ? a.fault_head + a.g_base + g : &kNoFault;
         const int fh = *fhp;
         // the group's first fault, staged in LDS once (fh is uniform outside
         // FT_SIGNAL, whose threads walk the list themselves)
@@ -1187,7 +1192,7 @@ template <typename R, int M, int KIND>
 __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
     constexpr int FP64 = sizeof(R) == 8;
     constexpr int C = cfg_C(FP64, M, KIND);
-    __shared__ cx<double> buf[2][M];
+    __shared__ cx<double> buf[M];  // the binary64 transform, in place
     __shared__ double scratch[kCorrThreads / 64];
     const int tid = threadIdx.x;
     const cx<R> *in = reinterpret_cast<const cx<R> *>(a.in);
@@ -1199,8 +1204,11 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
     if ((int64_t)nrec > a.rec_cap) nrec = a.rec_cap;
     for (int64_t i = blockIdx.x; i < (int64_t)nrec; i += gridDim.x) {
         const DevRecord rec = a.recs[i];
+        // records of this pass and of this launch's groups (a chunk of the
+        // batch covers groups g_base .. g_base + n_groups - 1)
         if (rec.pass != a.pass || rec.action != 1) continue;
-        const int64_t g = rec.group;
+        if (rec.group < a.g_base || rec.group >= a.g_base + a.n_groups) continue;
+        const int64_t g = rec.group - a.g_base;
 
         // applied output twiddle of member loc at output k (1 outside strided passes)
         auto applied = [&](const MemberLoc &L, int k) -> cx<double> {
@@ -1305,7 +1313,9 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
             return acc;
         };
 
-        // transform of the combined input, fp64, Stockham radix-2 in LDS
+        // transform of the combined input, fp64: radix-2 decimation in time in
+        // place in LDS (inputs stored at bit-reversed positions)
+        constexpr int LOGM = ilog2c(M);
         {
             const int step = IN_ALONG_MEMBERS ? kCorrThreads / CL : kCorrThreads;
             const int n0 = IN_ALONG_MEMBERS ? tid / CL : tid;
@@ -1314,35 +1324,34 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
                     return load_in(L, nn);
                 });
                 if (a.conj_in) acc.im = -acc.im;
-                if (!IN_ALONG_MEMBERS || tid % CL == 0) buf[0][n] = acc;
+                const int rn = LOGM == 0 ? 0 : (int)(__brev((unsigned)n) >> (32 - LOGM));
+                if (!IN_ALONG_MEMBERS || tid % CL == 0) buf[rn] = acc;
             }
         }
         __syncthreads();
-        int src = 0;
-        for (int ns = 1; ns < M; ns *= 2) {
+        for (int half = 1; half < M; half *= 2) {
             for (int t = tid; t < M / 2; t += kCorrThreads) {
-                const int kk = t & (ns - 1);
-                const cx<double> w = w64[kk * (M / (2 * ns))];
-                const cx<double> x0 = buf[src][t];
-                const cx<double> x1 = cmul(buf[src][t + M / 2], w);
-                const int o = (t / ns) * 2 * ns + kk;
-                buf[src ^ 1][o] = cadd(x0, x1);
-                buf[src ^ 1][o + ns] = csub(x0, x1);
+                const int kk = t & (half - 1);
+                const int i0 = (t - kk) * 2 + kk, i1 = i0 + half;
+                const cx<double> w = w64[kk * (M / (2 * half))];
+                const cx<double> x0 = buf[i0];
+                const cx<double> x1 = cmul(buf[i1], w);
+                buf[i0] = cadd(x0, x1);
+                buf[i1] = csub(x0, x1);
             }
             __syncthreads();
-            src ^= 1;
         }
         for (int kk = tid; kk < M; kk += kCorrThreads) {
-            cx<double> p = buf[src][kk];
+            cx<double> p = buf[kk];
             if (a.conj_out) p.im = -p.im;
             p.re *= a.out_scale;
             p.im *= a.out_scale;
-            buf[src][kk] = p;
+            buf[kk] = p;
         }
         __syncthreads();
 
         // P - sum of the (un-twiddled) outputs of the members other than jl
-        // (jl < 0: of all members) -> LDS buf[src ^ 1]
+        // (jl < 0: of all members), in place
         {
             const int step = OUT_ALONG_MEMBERS ? kCorrThreads / CL : kCorrThreads;
             const int k0 = OUT_ALONG_MEMBERS ? tid / CL : tid;
@@ -1351,7 +1360,7 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
                     const cx<double> y = cmulconj(load_out(L, k2), applied(L, k2));
                     return bm == jl ? cx<double>{0.0, 0.0} : y;
                 });
-                if (!OUT_ALONG_MEMBERS || tid % CL == 0) buf[src ^ 1][kk] = csub(buf[src][kk], s);
+                if (!OUT_ALONG_MEMBERS || tid % CL == 0) buf[kk] = csub(buf[kk], s);
             }
         }
         __syncthreads();
@@ -1360,14 +1369,14 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
         if (jl >= 0) {
             const MemberLoc Lj = member_loc<M, KIND, C>(a, g, jl);
             for (int kk = tid; kk < M; kk += kCorrThreads) {
-                const cx<double> y = cmul(buf[src ^ 1][kk], applied(Lj, kk));
+                const cx<double> y = cmul(buf[kk], applied(Lj, kk));
                 stg(out + Lj.out_off + (uint32_t)kk * Lj.out_stride, cx<R>{R(y.re), R(y.im)});
             }
             action = 2;
         } else {
             double nrm = 0.0;
             for (int kk = tid; kk < M; kk += kCorrThreads) {
-                const cx<double> v = buf[src ^ 1][kk];
+                const cx<double> v = buf[kk];
                 nrm += v.re * v.re + v.im * v.im;
             }
             nrm = block_sum(nrm, scratch);
@@ -1395,7 +1404,12 @@ template <typename R, int M, int KIND>
 static hipError_t launch_kind(int ft, const PassArgs &a, int grid, hipStream_t st) {
     if (ft == FT_BLOCK) return launch_one<R, M, KIND, FT_BLOCK>(a, grid, st);
     if (ft == FT_NONE) return launch_one<R, M, KIND, FT_NONE>(a, grid, st);
-    if (ft == FT_THREAD) return launch_one<R, M, KIND, FT_THREAD>(a, grid, st);
+    if (ft == FT_THREAD) {
+        // butterfly encodings exist for radix 2, 4 and 8 (plans of the
+        // thread-level scheme use no larger thread radix)
+        if constexpr (cfg_E(sizeof(R) == 8, M, KIND) <= 8) return launch_one<R, M, KIND, FT_THREAD>(a, grid, st);
+        else return hipErrorInvalidValue;
+    }
     if (ft == FT_SIGNAL) return launch_one<R, M, KIND, FT_SIGNAL>(a, grid, st);
     return hipErrorInvalidValue;
 }
@@ -1459,6 +1473,6 @@ int occ_m(int kind, int ft) {
     extern template hipError_t correct_m<R, M>(int, const PassArgs &, int, hipStream_t);     \
     extern template int occ_m<R, M>(int, int);
 #define TFFT_FOR_EACH_M(X, R) X(R, 2) X(R, 4) X(R, 8) X(R, 16) X(R, 32) X(R, 64) X(R, 128) X(R, 256) \
-    X(R, 512) X(R, 1024) X(R, 2048) X(R, 4096)
+    X(R, 512) X(R, 1024) X(R, 2048) X(R, 4096) X(R, 8192)
 
 }  // namespace tfft

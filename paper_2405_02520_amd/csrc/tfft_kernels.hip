@@ -32,6 +32,7 @@ static hipError_t by_m(int M, F &&f) {
         case 1024: return f(std::integral_constant<int, 1024>{});
         case 2048: return f(std::integral_constant<int, 2048>{});
         case 4096: return f(std::integral_constant<int, 4096>{});
+        case 8192: return f(std::integral_constant<int, 8192>{});
         default: return hipErrorInvalidValue;
     }
 }

@@ -102,6 +102,7 @@ struct tfft_plan_s {
     int timed_last = 0;          // the last execution was timed
     hipEvent_t ev[2 * kMaxPasses + 1] = {};
     int launched_correct = 0;
+    int64_t chunk = 0;           // multi-pass plans: signals per chunk of the batch (= batch: no chunking)
 };
 
 namespace {
@@ -303,7 +304,42 @@ struct Guard {
     }
 };
 
-int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, bool inverse) {
+// Geometry of pass P restricted to signals [c0, c0 + nb) of the batch: the
+// launch's outer units, groups, first group and workgroups.  Chunks start at
+// multiples of 64 signals, so no checksum group straddles two chunks.
+struct ChunkGeom {
+    int64_t n_outer, n_groups, g_base;
+    int grid;
+};
+
+ChunkGeom chunk_geom(const tfft_plan_s *p, const PassPlan &P, int64_t c0, int64_t nb) {
+    ChunkGeom c;
+    int64_t tiles;
+    if (P.kind == KIND_ROWS) {
+        c.n_outer = nb;
+        if (P.G == 1 && p->scheme == TFFT_SCHEME_SIGNAL) {
+            c.n_groups = nb;
+            c.g_base = c0;
+            tiles = (nb + P.C - 1) / P.C;
+        } else {
+            c.n_groups = (nb + P.G - 1) / P.G;
+            c.g_base = c0 / P.G;
+            tiles = c.n_groups;
+        }
+    } else {
+        const int64_t per = P.kind == KIND_STRIDED ? P.O : 1;  // outer units per signal
+        c.n_outer = nb * per;
+        c.n_groups = P.n_strips * ((c.n_outer + P.rb - 1) / P.rb);
+        c.g_base = P.n_strips * (c0 * per / P.rb);
+        tiles = c.n_groups;
+    }
+    int64_t grid = std::min<int64_t>(tiles, P.grid);
+    if (grid >= 8) grid = (grid + 7) / 8 * 8;
+    c.grid = (int)std::max<int64_t>(1, grid);
+    return c;
+}
+
+int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, bool inverse, void *work = nullptr) {
     if (!p || !d_in || !d_out) return TFFT_E_INVALID;
     if (mode < TFFT_FT_OFF || mode > TFFT_FT_CORRECT) return TFFT_E_INVALID;
     if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 15)) return TFFT_E_INVALID;
@@ -319,83 +355,101 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
     } else if ((a < b ? b - a : a - b) < bytes) {
         return TFFT_E_INVALID;  // partial overlap
     }
+    if (!work) work = p->d_work;
+    if (p->passes > 1 && !work) return TFFT_E_STATE;
     Guard guard(p->device);
     hipStream_t st = (hipStream_t)stream;
     const int fp64 = p->dtype == TFFT_C128;
     const int ft = mode != TFFT_FT_OFF;
     if (launch_reset(p->d_rep, st) != hipSuccess) return TFFT_E_HIP;
+    // one chunk (the whole batch) unless the plan chunks its multi-pass batch
+    const int64_t chunk = (p->passes > 1 && p->chunk > 0) ? p->chunk : p->batch;
     const bool timed = p->timing != 0;
+    const bool per_pass_events = timed && chunk >= p->batch;
     if (timed && hipEventRecord(p->ev[0], st) != hipSuccess) return TFFT_E_HIP;
-    for (int i = 0; i < p->passes; ++i) {
-        const PassPlan &P = p->pass[i];
-        const bool last = i == p->passes - 1;
-        PassArgs A;
-        std::memset(&A, 0, sizeof(A));
-        // every pass reads a buffer it does not write, so a flagged group can
-        // re-read its inputs: 1 pass in->out; 2 passes in->work->out;
-        // 3 passes in->out->work->out (out holds the pass-1 result meanwhile)
-        if (p->passes == 1) {
-            A.in = d_in;
-            A.out = d_out;
-        } else if (p->passes == 2) {
-            A.in = i == 0 ? d_in : p->d_work;
-            A.out = i == 0 ? p->d_work : d_out;
-        } else {
-            A.in = i == 0 ? d_in : (i == 1 ? (const void *)d_out : p->d_work);
-            A.out = i == 1 ? p->d_work : d_out;
+    const int scheme_ft = !ft ? FT_NONE
+                              : (p->scheme == TFFT_SCHEME_SIGNAL ? FT_SIGNAL
+                                                                 : (p->scheme == TFFT_SCHEME_THREAD ? FT_THREAD : FT_BLOCK));
+    const bool correct = mode == TFFT_FT_CORRECT && p->scheme != TFFT_SCHEME_THREAD;
+    for (int64_t c0 = 0; c0 < p->batch; c0 += chunk) {
+        const int64_t nb = std::min(chunk, p->batch - c0);
+        // the caller's buffers from signal c0 on (dense: an offset pointer;
+        // ragged class: the offset table from entry c0 on)
+        const size_t off = p->d_sig_off ? 0 : (size_t)c0 * (size_t)p->n * esz;
+        const void *cin = (const char *)d_in + off;
+        void *cout = (char *)d_out + off;
+        const int64_t *sig = p->d_sig_off ? p->d_sig_off + c0 : nullptr;
+        for (int i = 0; i < p->passes; ++i) {
+            const PassPlan &P = p->pass[i];
+            const bool last = i == p->passes - 1;
+            const ChunkGeom cg = chunk_geom(p, P, c0, nb);
+            PassArgs A;
+            std::memset(&A, 0, sizeof(A));
+            // every pass reads a buffer it does not write, so a flagged group can
+            // re-read its inputs: 1 pass in->out; 2 passes in->work->out;
+            // 3 passes in->out->work->out (out holds the pass-1 result meanwhile)
+            if (p->passes == 1) {
+                A.in = cin;
+                A.out = cout;
+            } else if (p->passes == 2) {
+                A.in = i == 0 ? cin : work;
+                A.out = i == 0 ? work : cout;
+            } else {
+                A.in = i == 0 ? cin : (i == 1 ? (const void *)cout : work);
+                A.out = i == 1 ? work : cout;
+            }
+            A.batch = nb;
+            A.n = p->n;
+            A.L = P.L;
+            A.S = P.S;
+            A.O = P.O;
+            A.rows = P.rows;
+            A.m1 = P.m1;
+            A.m2 = P.m2;
+            A.tw_scale = P.tw_scale;
+            A.n_outer = cg.n_outer;
+            // ragged classes address their signals through the offset table in
+            // the user buffers; the workspace is always dense [chunk][n]
+            A.in_sig = (A.in == cin || A.in == (const void *)cout) ? sig : nullptr;
+            A.out_sig = (A.out == cout) ? sig : nullptr;
+            A.G = P.G;
+            A.rb = P.rb;
+            A.n_strips = P.n_strips;
+            A.m1_log2 = ilog2_64(P.m1);
+            A.n_groups = cg.n_groups;
+            A.g_base = cg.g_base;
+            A.conj_in = inverse ? 1 : 0;
+            A.conj_out = inverse ? 1 : 0;
+            A.out_scale = (inverse && last && !(p->flags & TFFT_INVERSE_UNSCALED)) ? 1.0 / (double)p->n : 1.0;
+            A.cvec = !inverse ? P.d_cfwd : ((p->flags & TFFT_INVERSE_UNSCALED) ? P.d_cinv_unscaled : P.d_cinv);
+            A.stw = P.d_stw;
+            A.stw64 = P.d_stw64;
+            A.itw_lo = p->d_itw_lo;
+            A.itw_hi = p->d_itw_hi;
+            A.itw_bits = p->itw_bits;
+            A.pass = i;
+            A.tau_coef = P.tau_coef * A.out_scale;  // the outputs' rounding noise scales with them
+            A.rep = p->d_rep;
+            A.recs = p->d_recs;
+            A.rec_cap = p->rec_cap;
+            A.fault_head = P.d_fault_head;
+            A.faults = P.d_faults;
+            A.kappa_u = p->kappa * (fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
+            A.fix = mode == TFFT_FT_CORRECT;
+            if (launch_pass(fp64, P.M, P.kind, scheme_ft, A, cg.grid, st) != hipSuccess) return TFFT_E_HIP;
+            if (per_pass_events && hipEventRecord(p->ev[1 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
+            if (correct) {
+                // one workgroup per possible record, at most TFFT_CORRECT_GRID; a workgroup
+                // with no record of this pass and chunk exits at once
+                const int cgrid = (int)std::min<int64_t>(TFFT_CORRECT_GRID, std::max<int64_t>(1, cg.n_groups));
+                if (launch_correct(fp64, P.M, P.kind, A, cgrid, st) != hipSuccess) return TFFT_E_HIP;
+            }
+            if (per_pass_events && hipEventRecord(p->ev[2 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
         }
-        A.batch = p->batch;
-        A.n = p->n;
-        A.L = P.L;
-        A.S = P.S;
-        A.O = P.O;
-        A.rows = P.rows;
-        A.m1 = P.m1;
-        A.m2 = P.m2;
-        A.tw_scale = P.tw_scale;
-        A.n_outer = P.n_outer;
-        // ragged classes address their signals through the offset table in
-        // the user buffers; the workspace is always dense [batch][n]
-        A.in_sig = (A.in == d_in || A.in == (const void *)d_out) ? p->d_sig_off : nullptr;
-        A.out_sig = (A.out == d_out) ? p->d_sig_off : nullptr;
-        A.G = P.G;
-        A.rb = P.rb;
-        A.n_strips = P.n_strips;
-        A.m1_log2 = ilog2_64(P.m1);
-        A.n_groups = P.n_groups;
-        A.conj_in = inverse ? 1 : 0;
-        A.conj_out = inverse ? 1 : 0;
-        A.out_scale = (inverse && last && !(p->flags & TFFT_INVERSE_UNSCALED)) ? 1.0 / (double)p->n : 1.0;
-        A.cvec = !inverse ? P.d_cfwd : ((p->flags & TFFT_INVERSE_UNSCALED) ? P.d_cinv_unscaled : P.d_cinv);
-        A.stw = P.d_stw;
-        A.stw64 = P.d_stw64;
-        A.itw_lo = p->d_itw_lo;
-        A.itw_hi = p->d_itw_hi;
-        A.itw_bits = p->itw_bits;
-        A.pass = i;
-        A.tau_coef = P.tau_coef * A.out_scale;  // the outputs' rounding noise scales with them
-        A.rep = p->d_rep;
-        A.recs = p->d_recs;
-        A.rec_cap = p->rec_cap;
-        A.fault_head = P.d_fault_head;
-        A.faults = P.d_faults;
-        A.kappa_u = p->kappa * (fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
-        A.fix = mode == TFFT_FT_CORRECT;
-        const int scheme_ft = !ft ? FT_NONE
-                                  : (p->scheme == TFFT_SCHEME_SIGNAL ? FT_SIGNAL
-                                                                     : (p->scheme == TFFT_SCHEME_THREAD ? FT_THREAD : FT_BLOCK));
-        if (launch_pass(fp64, P.M, P.kind, scheme_ft, A, P.grid, st) != hipSuccess) return TFFT_E_HIP;
-        if (timed && hipEventRecord(p->ev[1 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
-        if (mode == TFFT_FT_CORRECT && p->scheme != TFFT_SCHEME_THREAD) {
-            // one workgroup per possible record, at most TFFT_CORRECT_GRID; a workgroup
-            // with no record of this pass exits at once
-            const int cgrid = (int)std::min<int64_t>(TFFT_CORRECT_GRID, std::max<int64_t>(1, P.n_groups));
-            if (launch_correct(fp64, P.M, P.kind, A, cgrid, st) != hipSuccess) return TFFT_E_HIP;
-        }
-        if (timed && hipEventRecord(p->ev[2 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
     }
-    p->timed_last = timed ? 1 : 0;
-    p->launched_correct = mode == TFFT_FT_CORRECT && p->scheme != TFFT_SCHEME_THREAD;
+    if (timed && !per_pass_events && hipEventRecord(p->ev[2 * p->passes], st) != hipSuccess) return TFFT_E_HIP;
+    p->timed_last = timed ? (per_pass_events ? 1 : 2) : 0;
+    p->launched_correct = correct;
     p->last_stream = st;
     p->executed = 1;
     p->last_mode = mode;
@@ -445,7 +499,8 @@ int shape_plan(tfft_plan_s *p, int64_t n, int64_t batch, int dtype, const tfft_o
     // the alternative schemes are not offered for ragged classes
     if (scheme != TFFT_SCHEME_BLOCK && ragged) return TFFT_E_UNSUPPORTED;
     const int k = ilog2_64(n);
-    if ((force_passes == 1 && k > 12) || (force_passes == 2 && (k < 8 || k > 20)) || (force_passes == 3 && k < 12))
+    if ((force_passes == 1 && k > TFFT_ONE_PASS_MAX_LOG2) || (force_passes == 2 && (k < 8 || k > 20)) ||
+        (force_passes == 3 && k < 12))
         return TFFT_E_UNSUPPORTED;
     p->n = n;
     p->batch = batch;
@@ -453,11 +508,18 @@ int shape_plan(tfft_plan_s *p, int64_t n, int64_t batch, int dtype, const tfft_o
     p->flags = flags;
     p->kappa = (opt && opt->kappa > 0) ? opt->kappa : (dtype == TFFT_C128 ? TFFT_KAPPA64 : TFFT_KAPPA32);
     p->scheme = scheme;
-    // one pass up to 2^12; two passes up to 2^19 (complex64) / 2^20; three
-    // passes above, the shortest first (tiles of the strided passes then hold
-    // >= 16 adjacent sub-signals, i.e. >= 128-byte segments per row)
+    // one pass up to 2^13 (the paper's single-launch limit); two passes up to
+    // 2^19 (complex64) / 2^20; three passes above, the shortest first (tiles
+    // of the strided passes then hold >= 16 adjacent sub-signals, i.e.
+    // >= 128-byte segments per row)
     const int two_max = dtype == TFFT_C128 ? TFFT_TWO_PASS_MAX_LOG2_64 : TFFT_TWO_PASS_MAX_LOG2_32;
-    const int npass = force_passes ? force_passes : (k <= 12 ? 1 : (k <= two_max ? 2 : 3));
+    // (the thread-level scheme checks radix-8 butterflies: its one-pass plans
+    // stop where the one-pass tile needs a larger thread radix)
+    const int one_max = (scheme == TFFT_SCHEME_THREAD && TFFT_ONE_PASS_MAX_LOG2 >= ilog2c(TFFT_E_ROWS_BIG_MIN))
+                            ? ilog2c(TFFT_E_ROWS_BIG_MIN) - 1
+                            : TFFT_ONE_PASS_MAX_LOG2;
+    if (force_passes == 1 && k > one_max) return TFFT_E_UNSUPPORTED;
+    const int npass = force_passes ? force_passes : (k <= one_max ? 1 : (k <= two_max ? 2 : 3));
     if (npass == 1) {
         p->passes = 1;
         p->lens[0] = (int)n;
@@ -477,7 +539,12 @@ int shape_plan(tfft_plan_s *p, int64_t n, int64_t batch, int dtype, const tfft_o
         const int rc = shape_pass(p, i, p->lens[i], kind, Guser, grid_scale);
         if (rc != TFFT_OK) return rc;
     }
-    p->work_bytes = p->passes > 1 ? (size_t)n * (size_t)batch * esz : 0;
+    // multi-pass plans may run their batch in chunks of whole signals, each
+    // chunk's passes through one workspace slot
+    const int32_t chunk = opt ? opt->chunk : 0;
+    if (chunk < 0 || chunk % 64 != 0) return TFFT_E_INVALID;
+    p->chunk = (p->passes > 1 && chunk > 0) ? std::min<int64_t>(chunk, batch) : batch;
+    p->work_bytes = p->passes > 1 ? (size_t)n * (size_t)p->chunk * esz : 0;
     int64_t cap = 0;
     for (int i = 0; i < p->passes; ++i)  // one-sided multi-pass: one record per sub-signal at most
         cap += p->pass[i].n_groups * ((p->scheme == TFFT_SCHEME_SIGNAL && p->pass[i].kind != KIND_ROWS) ? p->pass[i].G : 1);
@@ -741,6 +808,17 @@ int tfft_get_timings(tfft_plan p, double *pass_ms, double *correct_ms) {
     if (!p->executed || !p->timed_last) return TFFT_E_STATE;
     Guard guard(p->device);
     if (hipEventSynchronize(p->ev[2 * p->passes]) != hipSuccess) return TFFT_E_HIP;
+    if (p->timed_last == 2) {
+        // chunked execution: the passes of the chunks interleave; the whole
+        // execution is reported as pass 0
+        float a = 0.f;
+        if (hipEventElapsedTime(&a, p->ev[0], p->ev[2 * p->passes]) != hipSuccess) return TFFT_E_HIP;
+        for (int i = 0; i < kMaxPasses; ++i) {
+            if (pass_ms) pass_ms[i] = i == 0 ? a : 0.0;
+            if (correct_ms) correct_ms[i] = 0.0;
+        }
+        return TFFT_OK;
+    }
     for (int i = 0; i < kMaxPasses; ++i) {
         float a = 0.f, b = 0.f;
         if (i < p->passes) {
@@ -1054,7 +1132,7 @@ int tfft_ragged_tune(tfft_ragged r, const void *d_in, void *d_out, void *hip_str
         // candidates: pass count, checksum group size, workgroups per launch
         std::vector<tfft_options> cand;
         for (int ps = 1; ps <= 3; ++ps) {
-            if ((ps == 1 && k > 12) || (ps == 2 && (k < 8 || k > 20)) || (ps == 3 && k < 12)) continue;
+            if ((ps == 1 && k > TFFT_ONE_PASS_MAX_LOG2) || (ps == 2 && (k < 8 || k > 20)) || (ps == 3 && k < 12)) continue;
             for (int grp : {0, 16, 64})
                 for (int gs : {-1, 0, 1}) {
                     tfft_options o = r->opt;

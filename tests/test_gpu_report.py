@@ -190,3 +190,35 @@ def test_records_sorted_by_signal(tf):
     counts, recs = plan.report()
     assert counts["corrected"] == len(sigs)
     assert [r.signal for r in recs] == sorted(sigs)
+
+
+@pytest.mark.parametrize("dtype,log2n,B,chunk", [("c64", 14, 200, 64), ("c128", 16, 130, 64), ("c64", 20, 130, 64)])
+def test_chunked_execution_matches_whole_batch(tf, dtype, log2n, B, chunk):
+    """A multi-pass plan that runs its batch in chunks (one workspace slot of
+    `chunk` signals) gives bitwise the outputs of the whole-batch plan, and the
+    same records, with faults in several chunks and passes (group numbers are
+    those of the whole batch)."""
+    n = 1 << log2n
+    x = to_dev(inputs.uniform(9600 + log2n, B, n, NPDT[dtype]))
+    whole = tf.Plan(n, B, dtype)
+    part = tf.Plan(n, B, dtype, chunk=chunk)
+    info = whole.info()
+    assert part.info()["workspace_bytes"] == chunk * n * (8 if dtype == "c64" else 16)
+    rng = inputs.fault_rng(9600 + log2n)
+    faults = []
+    for sig in (3, 70, B - 1):
+        p = int(rng.integers(info["passes"]))
+        faults.append(dict(signal=sig, pass_=p, stage=-1, index=int(rng.integers(n)),
+                           value=math.sqrt(2.0 * math.prod(info["pass_len"][: p + 1]) / 3.0) * (0.6 + 0.8j)))
+    outs = []
+    for plan in (whole, part):
+        plan.set_faults(faults)
+        y = plan.forward(x, ft_mode="correct").cpu().numpy()
+        counts, recs = plan.report()
+        outs.append((y, counts, [(r.signal, r.sub, r.group, r.pass_, r.member, r.action) for r in recs]))
+    (ya, ca, ra), (yb, cb, rb) = outs
+    assert ca["corrected"] == len(faults) and ca == cb
+    assert ra == rb
+    assert np.array_equal(ya.view(np.uint8), yb.view(np.uint8))
+    sample = [3, 70, B - 1, 1, 64, 128]
+    assert oracle.rel_l2(ya[sample], oracle.fft(x.cpu().numpy()[sample].astype(np.complex128))) <= TOL[dtype]
