@@ -63,41 +63,76 @@ def parse():
 
 
 def cpu_baseline(sizes):
-    """The FP64 oracle (C radix-2, OpenMP over signals) on a bounded sample of
-    the same sweep: 2^26 elements of each size."""
+    """The FP64 oracle (C recursive radix-2, OpenMP over signals) on bounded
+    samples of the same sweep (the whole sweep would take hours on the host):
+    all host threads, median of 3 runs over max(1, 2^24 / N) signals of every
+    size; one thread, one run over max(1, 2^20 / N) signals of every size;
+    and the naive O(N^2) DFT on the correctness configuration (N = 256,
+    batch 64, all threads, median of 5)."""
     import numpy as np
 
     import oracle
     import tfft_inputs as inputs
 
     threads = oracle.max_threads()
-    flops = 0.0
-    t_total = 0.0
-    nsig_total = 0
-    for (dt, k) in sizes:
-        n = 1 << k
-        b = max(1, (1 << 26) // n)
-        x = inputs.uniform(inputs.sweep_seed(k, dt == "c128"), b, n, np.complex128)
+
+    def run(log2e, nthr, reps, kmax=24):
+        times, flops, nsig = [], 0.0, 0
+        xs = []
+        for (dt, k) in sizes:
+            if k > kmax:
+                continue
+            n = 1 << k
+            b = max(1, (1 << log2e) // n)
+            xs.append((inputs.uniform(inputs.sweep_seed(k, dt == "c128"), b, n, np.complex128), n, k, b))
+            flops += 5.0 * n * k * b
+            nsig += b
+        for _ in range(reps):
+            t = 0.0
+            for x, n, k, b in xs:
+                t0 = time.perf_counter()
+                oracle.fft(x, threads=nthr)
+                t += time.perf_counter() - t0
+            times.append(t)
+        return flops, sorted(times)[len(times) // 2], nsig
+
+    fl_all, t_all, ns_all = run(24, threads, 3)
+    fl_one, t_one, ns_one = run(20, 1, 1, kmax=20)
+    x1 = inputs.uniform(inputs.SEED_CORRECTNESS, 64, 256, np.complex128)
+    tn = []
+    for _ in range(5):
         t0 = time.perf_counter()
-        oracle.fft(x)
-        t_total += time.perf_counter() - t0
-        flops += 5.0 * n * k * b
-        nsig_total += b
-    return {"value": flops / t_total / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 recursive radix-2 oracle, {len(sizes)} sizes of the sweep, 2^26 elements per size "
-                      f"(OpenMP over signals), {nsig_total} signals, {t_total:.1f} s",
-            "seconds": t_total}
+        oracle.dft_naive(x1, threads=threads)
+        tn.append(time.perf_counter() - t0)
+    tn = sorted(tn)[2]
+    return {"value": round(fl_all / t_all / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 recursive radix-2 oracle over the {len(sizes)} sizes of the sweep, max(1, 2^24/N) "
+                      f"signals per size ({ns_all} signals), OpenMP over signals on all {threads} host threads, "
+                      f"median of 3 runs of {t_all:.2f} s; N = 2^23 and 2^24 offer 2 and 1 signals of parallelism",
+            "seconds": round(t_all, 3),
+            "one_core": {"value": round(fl_one / t_one / 1e9, 3), "unit": "GFLOP/s", "cores": 1,
+                         "sample": f"2^20 elements of every size N <= 2^20 ({ns_one} signals), one run of "
+                                   f"{t_one:.2f} s"},
+            "dft_naive_correctness_config": {"seconds": tn, "n": 256, "batch": 64, "cores": threads,
+                                             "GFLOPs_nominal": round(5.0 * 256 * 8 * 64 / tn / 1e9, 4)}}
+
+
+def kernel_source_sha():
+    """Hash of the device code and its compile-time configuration (the
+    kernel templates, their dispatch and the configuration header)."""
+    h = hashlib.sha256()
+    for f in ("tfft_kernels.h", "tfft_kernels.hip", "tfft_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2405_02520_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def pmc_traffic(kernel_key):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
-    src = os.path.join(ROOT, "paper_2405_02520_amd", "csrc", "tfft_kernels.hip")
     try:
         d = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if d.get("kernel_source_sha256") != sha:
+        if d.get("kernel_source_sha256") != kernel_source_sha():
             return None
         return d["entries"].get(kernel_key)
     except (OSError, ValueError, KeyError):
@@ -148,8 +183,7 @@ def summarize_pmc(root):
         vals = [c[ctr] * 1024 for k, c in runs.get("copy", {}).get(ctr, {}).items()
                 if "copybuffer" in k.lower() and ctr in c and c[ctr] * 1024 > 0.25 * copy_bytes]
         scale[ctr] = copy_bytes / max(vals) if vals else None
-    src = os.path.join(ROOT, "paper_2405_02520_amd", "csrc", "tfft_kernels.hip")
-    out = {"kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+    out = {"kernel_source_sha256": kernel_source_sha(),
            "copy_bytes": copy_bytes, "fetch_scale": scale["FETCH_SIZE"], "write_scale": scale["WRITE_SIZE"],
            "entries": {}}
     lines = [f"copy of {copy_bytes} B: FETCH_SIZE scale {scale['FETCH_SIZE']}, WRITE_SIZE scale {scale['WRITE_SIZE']}"]

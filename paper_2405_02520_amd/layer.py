@@ -34,29 +34,52 @@ def clear_plan_cache() -> None:
     _PLANS.clear()
 
 
+class UncorrectableError(RuntimeError):
+    """A flagged checksum group of the layer's transform was not corrected."""
+
+
+def _verify(plan: Plan, what: str) -> None:
+    counts, _ = plan.report()
+    if counts["uncorrectable"] or counts["dropped"]:
+        raise UncorrectableError(f"{what}: {counts}")
+
+
 class _FFTFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, x, ft_mode):
+    def forward(ctx, x, ft_mode, check):
         n = x.shape[-1]
         batch = x.numel() // n
         fwd, adj = _plans(n, batch, x.dtype, x.device)
         ctx.adj = adj
         ctx.ft_mode = ft_mode
+        ctx.check = check
         xc = x.contiguous()
-        return fwd.forward(xc, ft_mode=ft_mode).view(x.shape)
+        y = fwd.forward(xc, ft_mode=ft_mode).view(x.shape)
+        if check and ft_mode == "correct":
+            _verify(fwd, "forward transform")
+        return y
 
     @staticmethod
     def backward(ctx, gy):
         gx = ctx.adj.inverse(gy.contiguous(), ft_mode=ctx.ft_mode)
-        return gx.view(gy.shape), None
+        if ctx.check and ctx.ft_mode == "correct":
+            _verify(ctx.adj, "backward transform")
+        return gx.view(gy.shape), None, None
 
 
-def fft(x: torch.Tensor, ft_mode: str = "correct") -> torch.Tensor:
+def fft(x: torch.Tensor, ft_mode: str = "correct", check: bool = False) -> torch.Tensor:
     """Forward DFT along the last axis of a complex64/complex128 CUDA tensor,
-    differentiable, fault tolerant in both directions."""
+    differentiable, fault tolerant in both directions.
+
+    The outcome of the checks is in the plans' reports, which the layer does
+    not read by default (reading one waits for the transform's stream): call
+    ``last_reports()`` to see detected, corrected and uncorrectable groups.
+    With ``check=True`` (CORRECT mode) every forward and backward transform
+    reads its report and raises ``UncorrectableError`` when a flagged group
+    could not be corrected or a record was dropped."""
     if not x.is_complex():
         raise TypeError("fft expects a complex tensor")
-    return _FFTFunction.apply(x, ft_mode)
+    return _FFTFunction.apply(x, ft_mode, check)
 
 
 def last_reports():
