@@ -58,7 +58,9 @@ enum tfft_status {
     TFFT_E_UNSUPPORTED = -2, /* valid request this build does not implement */
     TFFT_E_NOMEM = -3,       /* device or host allocation failed */
     TFFT_E_HIP = -4,         /* a HIP runtime call failed */
-    TFFT_E_STATE = -5        /* call out of order (e.g. report before any exec) */
+    TFFT_E_STATE = -5,       /* call out of order (e.g. report before any exec) */
+    TFFT_E_SCRATCH = -6      /* tfft_exec_noalloc: the execution needs more than the
+                                static scratch (TFFT_SCRATCH_BYTES) */
 };
 
 /* Plan flags. */
@@ -231,6 +233,29 @@ int tfft_exec_forward(tfft_plan p, const void *d_in, void *d_out, int ft_mode, v
 
 /* Inverse transform (w_N^{-jn}; times 1/N unless TFFT_INVERSE_UNSCALED). */
 int tfft_exec_inverse(tfft_plan p, const void *d_in, void *d_out, int ft_mode, void *hip_stream);
+
+/* Size of the library's static device scratch: one array of this many bytes
+ * per device the library runs on, held until the process ends. */
+#define TFFT_SCRATCH_BYTES (64u << 20)
+
+/* Allocation-free execution, for callers that cannot allocate device memory
+ * while they run (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same transform, checks and outcome as
+ * tfft_exec_forward (inverse == 0) or tfft_exec_inverse (inverse != 0) on the
+ * same plan and buffers, but the execution's report counters, records and
+ * multi-pass workspace live in the library's static device scratch of
+ * TFFT_SCRATCH_BYTES instead of the plan's buffers; the call allocates
+ * nothing (no hipMalloc, no hipFree, no allocating library routine).  The
+ * caller passes the input and output buffers as for tfft_exec_forward.
+ * Returns E_SCRATCH when the report and workspace of the plan need more than
+ * TFFT_SCRATCH_BYTES (about 64 B per checksum group plus, for multi-pass
+ * plans, n * batch elements, or n * chunk with tfft_options.chunk), else as
+ * tfft_exec_forward.  Every call on one device shares that device's scratch
+ * and leaves the last call's contents there: tfft_get_report on this plan
+ * reads the scratch and is valid until the next tfft_exec_noalloc on the
+ * same device, and calls that overlap in time on one device (two streams,
+ * two threads) race. */
+int tfft_exec_noalloc(tfft_plan p, const void *d_in, void *d_out, int ft_mode, int inverse, void *hip_stream);
 
 /* Copy out the report of the last execution: counters into *counts (may be
  * NULL) and up to `cap` records, sorted by (signal, pass, group, sub), into

@@ -29,7 +29,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 C64, C128 = 0, 1
 FT_OFF, FT_DETECT, FT_CORRECT = 0, 1, 2
 OK, UNCORRECTABLE = 0, 1
-E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_STATE = -1, -2, -3, -4, -5
+E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_STATE, E_SCRATCH = -1, -2, -3, -4, -5, -6
+SCRATCH_BYTES = 64 << 20  # the library's static device scratch (tfft_exec_noalloc)
 INVERSE_UNSCALED = 1
 ACT_DETECTED, ACT_CORRECTED, ACT_BENIGN, ACT_UNCORRECTABLE = 1, 2, 3, 4
 LOC_NONE, LOC_QUOTIENT, LOC_PER_SIGNAL, LOC_THREAD, LOC_SUBSIGNAL = 0, 1, 2, 3, 4
@@ -88,6 +89,7 @@ _sig = {
     "tfft_plan_destroy": ([_P], ctypes.c_int),
     "tfft_exec_forward": ([_P, _P, _P, ctypes.c_int, _P], ctypes.c_int),
     "tfft_exec_inverse": ([_P, _P, _P, ctypes.c_int, _P], ctypes.c_int),
+    "tfft_exec_noalloc": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, _P], ctypes.c_int),
     "tfft_get_report": ([_P, ctypes.POINTER(tfft_counts), ctypes.POINTER(tfft_record), ctypes.c_int64],
                         ctypes.c_int),
     "tfft_set_faults": ([_P, ctypes.POINTER(tfft_fault), ctypes.c_int64], ctypes.c_int),
@@ -226,6 +228,19 @@ class Plan:
 
     def inverse(self, x, out=None, ft_mode="correct", stream=None):
         return self._exec(tfft_exec_inverse, x, out, ft_mode, stream)
+
+    def execute_noalloc(self, x, out, ft_mode="correct", inverse=False, stream=None):
+        """tfft_exec_noalloc: the transform with its report and workspace in
+        the library's static device scratch; ``out`` must be given (nothing
+        is allocated)."""
+        import torch
+        self._check_tensor(x, "input")
+        self._check_tensor(out, "output")
+        mode = _MODES[ft_mode] if isinstance(ft_mode, str) else int(ft_mode)
+        st = stream if stream is not None else torch.cuda.current_stream(x.device)
+        _check(tfft_exec_noalloc(self._h, x.data_ptr(), out.data_ptr(), mode, 1 if inverse else 0, st.cuda_stream),
+               "tfft_exec_noalloc")
+        return out
 
     def set_faults(self, faults):
         """faults: iterable of dicts with keys signal, pass_, stage, index and

@@ -27,7 +27,8 @@ COMMON = [
 ]
 # (source, extra defines, object name)
 LENGTHS = [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192]
-UNITS = [("tfft_kernels.hip", [], "tfft_kernels"), ("tfft_plan.cpp", [], "tfft_plan")] + [
+UNITS = [("tfft_kernels.hip", [], "tfft_kernels"), ("tfft_plan.cpp", [], "tfft_plan"),
+         ("tfft_scratch.hip", [], "tfft_scratch")] + [
     ("tfft_inst.hip", [f"-DTFFT_INST_R={r}", f"-DTFFT_INST_M={m}"], f"tfft_inst_{r}_{m}")
     for r in ("float", "double") for m in LENGTHS]
 

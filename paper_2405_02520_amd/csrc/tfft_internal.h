@@ -329,6 +329,14 @@ struct PassArgs {
 // Checksum schemes of a pass kernel (template argument FT).
 enum { FT_NONE = 0, FT_BLOCK = 1, FT_SIGNAL = 2, FT_THREAD = 3 };
 
+// Size of the library's static device scratch (one copy per device), the
+// memory of the allocation-free entry point: report counters, records and
+// multi-pass workspace of one execution.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+// Device address of the scratch on `device` (the current device); NULL on
+// failure.
+void *scratch_address(int device);
+
 // Host-side launchers (defined in the kernel translation unit).
 hipError_t launch_pass(int fp64, int M, int kind, int ft, const PassArgs &a, int grid, hipStream_t st);
 hipError_t launch_correct(int fp64, int M, int kind, const PassArgs &a, int grid, hipStream_t st);

@@ -20,6 +20,8 @@
 using namespace tfft;
 using cd = std::complex<double>;
 
+static_assert(kScratchBytes == TFFT_SCRATCH_BYTES, "static scratch size as declared in the header");
+
 namespace {
 
 // exp(-2 pi i t / n) for integers t, n.  The argument is split into a
@@ -92,6 +94,8 @@ struct tfft_plan_s {
     DevReport *d_rep = nullptr;
     DevRecord *d_recs = nullptr;
     int64_t rec_cap = 0;
+    DevReport *rep_last = nullptr;  // report buffers of the last execution (the plan's or the static scratch)
+    DevRecord *recs_last = nullptr;
     hipStream_t last_stream = nullptr;
     int executed = 0;
     int last_mode = 0;
@@ -339,7 +343,16 @@ ChunkGeom chunk_geom(const tfft_plan_s *p, const PassPlan &P, int64_t c0, int64_
     return c;
 }
 
-int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, bool inverse, void *work = nullptr) {
+// Device buffers of one execution: the report counters, the records and the
+// multi-pass workspace (the plan's own, or parts of the static scratch).
+struct ExecBufs {
+    DevReport *rep;
+    DevRecord *recs;
+    void *work;
+};
+
+int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, bool inverse,
+         const ExecBufs *bufs = nullptr) {
     if (!p || !d_in || !d_out) return TFFT_E_INVALID;
     if (mode < TFFT_FT_OFF || mode > TFFT_FT_CORRECT) return TFFT_E_INVALID;
     if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 15)) return TFFT_E_INVALID;
@@ -355,13 +368,15 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
     } else if ((a < b ? b - a : a - b) < bytes) {
         return TFFT_E_INVALID;  // partial overlap
     }
-    if (!work) work = p->d_work;
+    void *work = bufs ? bufs->work : p->d_work;
+    DevReport *rep = bufs ? bufs->rep : p->d_rep;
+    DevRecord *recs = bufs ? bufs->recs : p->d_recs;
     if (p->passes > 1 && !work) return TFFT_E_STATE;
     Guard guard(p->device);
     hipStream_t st = (hipStream_t)stream;
     const int fp64 = p->dtype == TFFT_C128;
     const int ft = mode != TFFT_FT_OFF;
-    if (launch_reset(p->d_rep, st) != hipSuccess) return TFFT_E_HIP;
+    if (launch_reset(rep, st) != hipSuccess) return TFFT_E_HIP;
     // one chunk (the whole batch) unless the plan chunks its multi-pass batch
     const int64_t chunk = (p->passes > 1 && p->chunk > 0) ? p->chunk : p->batch;
     const bool timed = p->timing != 0;
@@ -429,8 +444,8 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
             A.itw_bits = p->itw_bits;
             A.pass = i;
             A.tau_coef = P.tau_coef * A.out_scale;  // the outputs' rounding noise scales with them
-            A.rep = p->d_rep;
-            A.recs = p->d_recs;
+            A.rep = rep;
+            A.recs = recs;
             A.rec_cap = p->rec_cap;
             A.fault_head = P.d_fault_head;
             A.faults = P.d_faults;
@@ -450,6 +465,8 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
     if (timed && !per_pass_events && hipEventRecord(p->ev[2 * p->passes], st) != hipSuccess) return TFFT_E_HIP;
     p->timed_last = timed ? (per_pass_events ? 1 : 2) : 0;
     p->launched_correct = correct;
+    p->rep_last = rep;
+    p->recs_last = recs;
     p->last_stream = st;
     p->executed = 1;
     p->last_mode = mode;
@@ -471,6 +488,7 @@ const char *tfft_status_string(int s) {
         case TFFT_E_NOMEM: return "out of memory";
         case TFFT_E_HIP: return "HIP runtime error";
         case TFFT_E_STATE: return "call out of order";
+        case TFFT_E_SCRATCH: return "the execution needs more than the library's static scratch (64 MiB per device)";
         default: return "unknown status";
     }
 }
@@ -639,17 +657,36 @@ int tfft_exec_inverse(tfft_plan p, const void *d_in, void *d_out, int ft_mode, v
     return exec(p, d_in, d_out, ft_mode, hip_stream, true);
 }
 
+// The same execution with its report and workspace in the static scratch:
+// [report counters | records | workspace], each part 256-byte aligned.  No
+// allocation of any kind; the counters are cleared by the reset kernel of
+// the execution itself.
+int tfft_exec_noalloc(tfft_plan p, const void *d_in, void *d_out, int ft_mode, int inverse, void *hip_stream) {
+    if (!p) return TFFT_E_INVALID;
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t rep_bytes = up(sizeof(DevReport));
+    const size_t rec_bytes = up(sizeof(DevRecord) * (size_t)p->rec_cap);
+    const size_t work_bytes = p->passes > 1 ? up(p->work_bytes) : 0;
+    if (rep_bytes + rec_bytes + work_bytes > kScratchBytes) return TFFT_E_SCRATCH;
+    Guard guard(p->device);
+    unsigned char *base = static_cast<unsigned char *>(scratch_address(p->device));
+    if (!base) return TFFT_E_HIP;
+    const ExecBufs b{reinterpret_cast<DevReport *>(base), reinterpret_cast<DevRecord *>(base + rep_bytes),
+                     work_bytes ? base + rep_bytes + rec_bytes : nullptr};
+    return exec(p, d_in, d_out, ft_mode, hip_stream, inverse != 0, &b);
+}
+
 int tfft_get_report(tfft_plan p, tfft_counts *counts, tfft_record *recs, int64_t cap) {
     if (!p || cap < 0 || (cap > 0 && !recs)) return TFFT_E_INVALID;
     if (!p->executed) return TFFT_E_STATE;
     Guard guard(p->device);
     if (hipStreamSynchronize(p->last_stream) != hipSuccess) return TFFT_E_HIP;
     DevReport h;
-    if (hipMemcpy(&h, p->d_rep, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return TFFT_E_HIP;
+    if (hipMemcpy(&h, p->rep_last, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return TFFT_E_HIP;
     const int64_t nrec = std::min<int64_t>((int64_t)h.n_flag, p->rec_cap);
     std::vector<DevRecord> dr((size_t)nrec);
     if (nrec > 0 &&
-        hipMemcpy(dr.data(), p->d_recs, sizeof(DevRecord) * (size_t)nrec, hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(dr.data(), p->recs_last, sizeof(DevRecord) * (size_t)nrec, hipMemcpyDeviceToHost) != hipSuccess)
         return TFFT_E_HIP;
     int64_t groups = 0;
     if (p->last_mode != TFFT_FT_OFF)

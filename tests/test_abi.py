@@ -46,7 +46,13 @@ def test_version_and_status_strings(tf):
     assert tf.tfft_version() == 1
     assert tf.tfft_status_string(tf.OK) == b"ok"
     assert b"invalid" in tf.tfft_status_string(tf.E_INVALID)
+    assert b"scratch" in tf.tfft_status_string(tf.E_SCRATCH)
     assert tf.tfft_status_string(12345) == b"unknown status"
+
+
+def test_noalloc_rejects_a_null_plan(tf):
+    """Argument check before any device work."""
+    assert tf.tfft_exec_noalloc(None, None, None, tf.FT_CORRECT, 0, None) == tf.E_INVALID
 
 
 @pytest.mark.parametrize("n,batch,dtype", [(0, 1, 0), (3, 1, 0), (12, 4, 0), (1 << 25, 1, 0), (1024, 0, 0),
