@@ -65,7 +65,9 @@ enum tfft_status {
 
 /* Plan flags. */
 enum tfft_flags {
-    TFFT_INVERSE_UNSCALED = 1u << 0 /* exec_inverse omits the 1/N factor */
+    TFFT_INVERSE_UNSCALED = 1u << 0, /* exec_inverse omits the 1/N factor */
+    TFFT_PERSISTENT = 1u << 1        /* ragged plans only: every class's passes run in one
+                                        persistent kernel launch draining a work queue */
 };
 
 /* Record actions. */
@@ -120,7 +122,10 @@ typedef struct {
                         multiple of 64), each chunk's passes through one workspace slot of
                         chunk * n elements; 0 = the whole batch at once.  Faults, records
                         and group numbers are those of the whole batch. */
-    int32_t reserved[4];
+    int32_t split;   /* multi-pass plans: 0 = the default split N = M_1..M_P (shortest
+                        first); 1 = the alternative (two passes: the longer first; three
+                        passes: the middle length first), a tuning knob */
+    int32_t reserved[3];
 } tfft_options;
 
 /* Description of a plan (tfft_plan_info). */
@@ -360,6 +365,14 @@ int tfft_ragged_tune(tfft_ragged r, const void *d_in, void *d_out, void *hip_str
  * description (arrays may be NULL). */
 int tfft_ragged_info(tfft_ragged r, int64_t *classes, int64_t *lengths, int64_t *counts, tfft_plan_desc *descs,
                      int64_t cap);
+
+/* Measurement instrument: copy `bytes` from d_src to d_dst (device buffers,
+ * 16-byte aligned, not overlapping) with a plain streaming kernel that moves
+ * data the way the pass kernels do (16-byte non-temporal loads and stores,
+ * several in flight per thread, many workgroups); the bandwidth it reaches
+ * is the attainable HBM ceiling quoted next to the peak.  Asynchronous on
+ * hip_stream.  E_INVALID for NULL, misaligned or overlapping buffers. */
+int tfft_stream_copy(void *d_dst, const void *d_src, size_t bytes, void *hip_stream);
 
 /* Static text for a status code. */
 const char *tfft_status_string(int status);

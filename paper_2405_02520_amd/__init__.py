@@ -17,7 +17,9 @@ import warnings
 from dataclasses import dataclass
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtfft.so")
+# TFFT_LIB selects another build of the library (a compile-time variant);
+# the default is the in-tree build next to this file.
+LIB_PATH = os.environ.get("TFFT_LIB") or os.path.join(_HERE, "libtfft.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -32,6 +34,7 @@ OK, UNCORRECTABLE = 0, 1
 E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_STATE, E_SCRATCH = -1, -2, -3, -4, -5, -6
 SCRATCH_BYTES = 64 << 20  # the library's static device scratch (tfft_exec_noalloc)
 INVERSE_UNSCALED = 1
+PERSISTENT = 2
 ACT_DETECTED, ACT_CORRECTED, ACT_BENIGN, ACT_UNCORRECTABLE = 1, 2, 3, 4
 LOC_NONE, LOC_QUOTIENT, LOC_PER_SIGNAL, LOC_THREAD, LOC_SUBSIGNAL = 0, 1, 2, 3, 4
 SCHEME_BLOCK, SCHEME_SIGNAL, SCHEME_THREAD = 0, 1, 2
@@ -44,7 +47,7 @@ _MODES = {"off": FT_OFF, "detect": FT_DETECT, "correct": FT_CORRECT}
 class tfft_options(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("group", ctypes.c_int32), ("kappa", ctypes.c_double),
                 ("passes", ctypes.c_int32), ("grid_scale", ctypes.c_int32), ("scheme", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("chunk", ctypes.c_int32), ("split", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 MAX_PASSES = 3
@@ -112,6 +115,7 @@ _sig = {
     "tfft_host_root": ([ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tfft_host_checksum_vector": ([ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
                                   ctypes.c_int),
+    "tfft_stream_copy": ([_P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "tfft_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "tfft_version": ([], ctypes.c_int),
 }
@@ -164,7 +168,7 @@ class Plan:
 
     def __init__(self, n: int, batch: int, dtype="c64", group: int = 0, kappa: float = 0.0,
                  inverse_unscaled: bool = False, passes: int = 0, grid_scale: int = 0, scheme="block",
-                 chunk: int = 0):
+                 chunk: int = 0, split: int = 0):
         """scheme: "block" (two-sided, per group of signals), "signal"
         (one-sided, per signal or sub-signal) or "thread" (per radix
         butterfly).  chunk: multi-pass plans run the batch in chunks of this
@@ -173,7 +177,8 @@ class Plan:
         self.dtype_code = _dtype_code(dtype)
         sch = _SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         opt = tfft_options(flags=INVERSE_UNSCALED if inverse_unscaled else 0, group=int(group), kappa=float(kappa),
-                           passes=int(passes), grid_scale=int(grid_scale), scheme=sch, chunk=int(chunk))
+                           passes=int(passes), grid_scale=int(grid_scale), scheme=sch, chunk=int(chunk),
+                           split=int(split))
         h = _P()
         _check(tfft_plan_create_with(ctypes.byref(h), self.n, self.batch, self.dtype_code, ctypes.byref(opt)),
                "tfft_plan_create_with")
@@ -297,7 +302,10 @@ class Ragged:
     plan addressing its signals through a device offset table; ``use_graph``
     replays all launches of all classes as one captured HIP graph."""
 
-    def __init__(self, lengths, offsets=None, dtype="c64", group: int = 0, kappa: float = 0.0):
+    def __init__(self, lengths, offsets=None, dtype="c64", group: int = 0, kappa: float = 0.0,
+                 persistent: bool = False):
+        """persistent: every pass of every class runs in one persistent kernel
+        launch that drains a queue of work items (lengths 64..2^24)."""
         import numpy as np
         self.lengths = np.asarray(lengths, dtype=np.int64)
         if offsets is None:
@@ -306,7 +314,8 @@ class Ragged:
         self.count = int(len(self.lengths))
         self.extent = int((self.offsets + self.lengths).max()) if self.count else 0
         self.dtype_code = _dtype_code(dtype)
-        opt = tfft_options(group=int(group), kappa=float(kappa))
+        opt = tfft_options(flags=PERSISTENT if persistent else 0, group=int(group), kappa=float(kappa))
+        self.persistent = bool(persistent)
         ln = np.ascontiguousarray(self.lengths)
         h = _P()
         _check(tfft_ragged_create(ctypes.byref(h), self.count,
@@ -399,11 +408,12 @@ class Ragged:
 
 
 def describe(n: int, batch: int, dtype="c64", group: int = 0, kappa: float = 0.0, passes: int = 0,
-             grid_scale: int = 0, scheme="block") -> dict:
+             grid_scale: int = 0, scheme="block", split: int = 0) -> dict:
     """The plan description (as ``Plan.info``) of a plan with these
     arguments, computed on the host without a device."""
     sch = _SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
-    opt = tfft_options(group=int(group), kappa=float(kappa), passes=int(passes), grid_scale=int(grid_scale), scheme=sch)
+    opt = tfft_options(group=int(group), kappa=float(kappa), passes=int(passes), grid_scale=int(grid_scale), scheme=sch,
+                       split=int(split))
     d = tfft_plan_desc()
     _check(tfft_plan_describe(int(n), int(batch), _dtype_code(dtype), ctypes.byref(opt), ctypes.byref(d)),
            "tfft_plan_describe")

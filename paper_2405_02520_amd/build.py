@@ -30,7 +30,9 @@ LENGTHS = [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192]
 UNITS = [("tfft_kernels.hip", [], "tfft_kernels"), ("tfft_plan.cpp", [], "tfft_plan"),
          ("tfft_scratch.hip", [], "tfft_scratch")] + [
     ("tfft_inst.hip", [f"-DTFFT_INST_R={r}", f"-DTFFT_INST_M={m}"], f"tfft_inst_{r}_{m}")
-    for r in ("float", "double") for m in LENGTHS]
+    for r in ("float", "double") for m in LENGTHS] + [
+    ("tfft_persist_inst.hip", [f"-DTFFT_INST_R={r}", f"-DTFFT_INST_FT={ft}"], f"tfft_persist_{r}_{ft}")
+    for r in ("float", "double") for ft in ("FT_NONE", "FT_BLOCK")]
 
 
 def _compile(src: str, defs: list[str], obj: str, extra: list[str]) -> str:
@@ -53,7 +55,8 @@ def build(resource_usage: bool = False, verbose: bool = False, defines=(), lib: 
     jobs = int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 4
     # the longest units first
     order = sorted(range(len(UNITS)), key=lambda i: -max([int(d.split("=")[1]) for d in UNITS[i][1]
-                                                          if d.startswith("-DTFFT_INST_M")] or [8192]))
+                                                          if d.startswith("-DTFFT_INST_M")] or
+                                                         [16384 if "persist" in UNITS[i][2] else 8192]))
     with ThreadPoolExecutor(max_workers=min(jobs, len(UNITS))) as ex:
         futs = {i: ex.submit(_compile, UNITS[i][0], UNITS[i][1], objs[i], extra) for i in order}
         logs = [futs[i].result() for i in range(len(UNITS))]

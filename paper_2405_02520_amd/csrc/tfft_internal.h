@@ -132,6 +132,16 @@ constexpr int cfg_C(int fp64, int M, int kind) {
 #ifndef TFFT_NT_MIN_ROW
 #define TFFT_NT_MIN_ROW 128
 #endif
+// Member addressing of multi-pass tiles by shifts and masks (1) or by 64-bit
+// divisions (0); n_strips and O are powers of two.
+#ifndef TFFT_MEMBER_SHIFT
+#define TFFT_MEMBER_SHIFT 0
+#endif
+// Strided passes (whose outputs the next pass reads) store streaming (1) or
+// through the caches (0).
+#ifndef TFFT_NT_STRIDED_ST
+#define TFFT_NT_STRIDED_ST 1
+#endif
 // Total threads of one launch when it is not persistent (workgroups capped
 // at this divided by the workgroup size).
 #ifndef TFFT_GRID_THREADS
@@ -163,6 +173,12 @@ constexpr int cfg_C(int fp64, int M, int kind) {
 #endif
 #ifndef TFFT_KAPPA64
 #define TFFT_KAPPA64 96.0
+#endif
+// Workgroups (of 512 threads) of the streaming copy instrument (measured:
+// 16384 workgroups of 512 threads, four 16-byte elements in flight per
+// thread, reach the highest copy bandwidth).
+#ifndef TFFT_COPY_GRID
+#define TFFT_COPY_GRID 16384
 #endif
 // Parallel branches of a captured ragged graph (independent length classes).
 #ifndef TFFT_GRAPH_BRANCHES
@@ -264,6 +280,7 @@ constexpr int stage_ns(int M, int E, int s) { return s <= n_full(M, E) ? ipowc(E
 struct DevRecord {
     int64_t group;
     int32_t pass, action, member, method;
+    int32_t task, pad_;  // persistent ragged kernel: the (class, pass) task; 0 otherwise
     double d1r, d1i, d2r, d2i, tau, s;
 };
 
@@ -324,10 +341,45 @@ struct PassArgs {
     int32_t m1_log2;    // LAST: log2(m1), so that the row map shifts instead of dividing
     int64_t g_base;     // index of this launch's first group within the pass (a chunk of the
                         // batch): fault lookup and records use g_base + g
+    int32_t task;       // persistent ragged kernel: task index carried by the records (0 otherwise)
+    int32_t ns_log2;    // multi-pass: log2(n_strips)
+    int32_t o_log2;     // STRIDED: log2(O)
+    int32_t pad_;
 };
 
 // Checksum schemes of a pass kernel (template argument FT).
 enum { FT_NONE = 0, FT_BLOCK = 1, FT_SIGNAL = 2, FT_THREAD = 3 };
+
+// ------------------------------------------------ persistent ragged queue
+// A task is one pass of one length class of a ragged batch; an item is a
+// range of the task's checksum groups; a chunk is a block of the class's
+// signals (a multiple of 64, so that no group straddles two chunks) whose
+// items of pass p must all be released before its items of pass p + 1 start.
+struct PItem {
+    int32_t task;
+    int32_t chunk;
+    int64_t g0, g1;  // groups [g0, g1) of the task's pass
+};
+struct PTask {
+    PassArgs a;         // the pass: tables, buffers, geometry, report (g_base = 0)
+    int32_t variant;    // compiled kernel variant, pvariant_id(kind, M)
+    int32_t dep;        // task of the previous pass of the same class, -1 for none
+    int32_t done_base;  // index of this task's chunk 0 in the done / need arrays
+    int32_t fix;        // correct flagged groups before releasing the item
+};
+struct PQueue {
+    const PItem *items;
+    int64_t n_items;
+    const PTask *tasks;
+    unsigned long long *head;  // next item to take
+    int32_t *done;             // items released, per (task, chunk)
+    const int32_t *need;       // items, per (task, chunk)
+    int32_t *err;              // bit 0: a dependency wait ran out; bit 1: unknown variant
+    int64_t spin_limit;        // polls of a dependency wait before it gives up
+};
+constexpr int pvariant_id(int kind, int M) { return kind * 16 + ilog2c(M); }
+constexpr int kPersistThreads = 512;  // threads of the persistent workgroup
+constexpr int kPSlotCap = 64;         // groups per item (each flags at most one record)
 
 // Size of the library's static device scratch (one copy per device), the
 // memory of the allocation-free entry point: report counters, records and
@@ -341,6 +393,13 @@ void *scratch_address(int device);
 hipError_t launch_pass(int fp64, int M, int kind, int ft, const PassArgs &a, int grid, hipStream_t st);
 hipError_t launch_correct(int fp64, int M, int kind, const PassArgs &a, int grid, hipStream_t st);
 hipError_t launch_reset(DevReport *rep, hipStream_t st);
+// Persistent ragged kernel: launch over `grid` workgroups, its resident
+// workgroups per compute unit, and the reset of its queue state and report.
+hipError_t launch_persist(int fp64, int ft, const PQueue &q, int grid, hipStream_t st);
+int persist_occupancy(int fp64, int ft);
+hipError_t launch_persist_reset(const PQueue &q, int n_done, DevReport *rep, hipStream_t st);
+// Streaming device copy of `bytes` (measurement instrument).
+hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 // Resident workgroups of a pass kernel per compute unit (0 on error).
 int pass_occupancy(int fp64, int M, int kind, int ft);
 

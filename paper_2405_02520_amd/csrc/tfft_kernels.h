@@ -195,12 +195,15 @@ __device__ __forceinline__ MemberLoc member_loc(const PassArgs &a, int64_t g, in
         L.out_stride = 1;
         L.tw_i = 0;
     } else {
-        const int64_t strip = g % a.n_strips;
-        const int64_t u = (g / a.n_strips) * a.rb + b / C;  // outer unit
+        // n_strips and O are powers of two: shifts and masks (TFFT_MEMBER_SHIFT)
+        // or divisions
+        const int64_t strip = TFFT_MEMBER_SHIFT ? (g & (a.n_strips - 1)) : g % a.n_strips;
+        const int64_t u = (TFFT_MEMBER_SHIFT ? (g >> a.ns_log2) : g / a.n_strips) * a.rb + b / C;  // outer unit
         const int64_t r = strip * C + b % C;                 // sub-signal inside the unit
         L.valid = u < a.n_outer;
         if constexpr (KIND == KIND_STRIDED) {
-            const int64_t beta = L.valid ? u / a.O : 0, o = u % a.O;
+            const int64_t beta = L.valid ? (TFFT_MEMBER_SHIFT ? (u >> a.o_log2) : u / a.O) : 0;
+            const int64_t o = TFFT_MEMBER_SHIFT ? (u & (a.O - 1)) : u % a.O;
             L.in_off = (a.in_sig ? a.in_sig[beta] : beta * a.n) + o * a.L + r;
             L.out_off = (a.out_sig ? a.out_sig[beta] : beta * a.n) + o * a.L + r;
             L.in_stride = (uint32_t)a.S;
@@ -487,6 +490,7 @@ __device__ __forceinline__ void thread_check(cx<R> (&d)[E], const cx<R> (&vin)[E
             DevRecord rc;
             rc.group = a.g_base + g;
             rc.pass = a.pass;
+            rc.task = a.task;
             rc.action = a.fix ? 2 : 1;  // corrected in registers, or detected
             rc.member = b;
             rc.method = 3;  // located inside the thread's butterfly
@@ -516,42 +520,106 @@ __device__ __forceinline__ void thread_check(cx<R> (&d)[E], const cx<R> (&vin)[E
 #else
 #define TFFT_PASS_OCCUPANCY
 #endif
-template <typename R, int M, int KIND, int FT>
-__global__ void __launch_bounds__(cfg_threads(sizeof(R) == 8, M, KIND)) TFFT_PASS_OCCUPANCY
-pass_kernel(PassArgs a) {
-    constexpr int FP64 = sizeof(R) == 8;
-    constexpr bool BLK = FT == FT_BLOCK, SIG = FT == FT_SIGNAL, THR = FT == FT_THREAD;
-    constexpr bool PF_FENCE = cfg_pf_fence(FP64, M, KIND) != 0;
+// Compile-time shape of a pass kernel.  NTHR = 0: the tile of the dense
+// configuration (cfg_C); NTHR > 0: tiles of NTHR / T signals, so that every
+// variant fills a workgroup of NTHR threads (the persistent ragged kernel).
+template <typename R, int M, int KIND, int FT, int NTHR = 0>
+struct PassCfg {
+    static constexpr int FP64 = sizeof(R) == 8;
+    static constexpr bool BLK = FT == FT_BLOCK, SIG = FT == FT_SIGNAL, THR = FT == FT_THREAD;
+    static constexpr bool PF_FENCE = cfg_pf_fence(FP64, M, KIND) != 0;
+    static constexpr int E = cfg_E(FP64, M, KIND);
+    static constexpr int T = M / E;
+    static constexpr int C = NTHR > 0 ? (NTHR / T > 0 ? NTHR / T : 1) : cfg_C(FP64, M, KIND);
+    static constexpr int NT = C * T;
     // Non-temporal stores, except for tiles whose rows are narrower than a
     // 128-byte line: there the two halves of a line come from different
     // workgroups and must meet in L2 (measured: streaming them wrote up to
     // 26% more bytes than the output holds).
-    constexpr bool NT_ST = KIND == KIND_ROWS || cfg_C(FP64, M, KIND) * int(sizeof(cx<R>)) >= TFFT_NT_MIN_ROW;
-    constexpr bool ENC = BLK || SIG;  // input and output encodings
-    constexpr bool SIGR = SIG && KIND == KIND_ROWS;  // one-sided, tiles of one-signal groups
-    constexpr bool SIGM = SIG && KIND != KIND_ROWS;  // one-sided, per sub-signal of block tiles
-    constexpr int E = cfg_E(FP64, M, KIND);
-    constexpr int T = M / E;
-    constexpr int C = cfg_C(FP64, M, KIND);
-    constexpr int NT = C * T;
-    using St = Stages<M, E>;
-    constexpr int NSTAGE = St::count;
-    constexpr int WAVES = (NT + 63) / 64;
-    constexpr int WIDTH = NT < 64 ? NT : 64;
+    static constexpr bool NT_ST = KIND == KIND_ROWS || (C * int(sizeof(R)) * 2 >= TFFT_NT_MIN_ROW &&
+                                                        (KIND == KIND_LAST || TFFT_NT_STRIDED_ST));
+    static constexpr bool ENC = BLK || SIG;          // input and output encodings
+    static constexpr bool SIGR = SIG && KIND == KIND_ROWS;  // one-sided, tiles of one-signal groups
+    static constexpr bool SIGM = SIG && KIND != KIND_ROWS;  // one-sided, per sub-signal of block tiles
+    static constexpr int NSTAGE = n_stages(M, E);
+    static constexpr int WAVES = (NT + 63) / 64;
+    static constexpr int WIDTH = NT < 64 ? NT : 64;
     // group sums reduced through LDS (see the end of a group)
-    constexpr bool LDS_RED = TFFT_LDS_RED && NT % 64 == 0 && NT > 64 &&
-                             C * M * int(sizeof(cx<R>)) >= 5 * NT * int(sizeof(double));
-
+    static constexpr bool LDS_RED = TFFT_LDS_RED && NT % 64 == 0 && NT > 64 &&
+                                    C * M * int(sizeof(R)) * 2 >= 5 * NT * int(sizeof(double));
     // block scheme: a group's decision deferred into the next group, which
     // needs at least one workgroup barrier inside every group
-    constexpr bool RED_DEFER = TFFT_RED_DEFER && BLK && !LDS_RED && NT % 64 == 0 &&
-                               (NSTAGE >= 2 || KIND == KIND_LAST);
+    static constexpr bool RED_DEFER = TFFT_RED_DEFER && BLK && !LDS_RED && NT % 64 == 0 &&
+                                      (NSTAGE >= 2 || KIND == KIND_LAST);
+    static constexpr bool TWREG = cfg_twreg(FP64, M, KIND) != 0;
+    static constexpr bool CREG = ENC && cfg_creg(FP64, M, KIND) != 0;
+    // prefetch of the next tile straight into a second LDS buffer (16-byte
+    // elements, whole wavefronts, both buffers within 128 KiB)
+    static constexpr bool LDSPF = FP64 && (TFFT_LDSPF64 == 2 || (TFFT_LDSPF64 == 1 && KIND == KIND_ROWS)) &&
+                                  M >= TFFT_LDSPF64_MIN && C * M * 16 * 2 <= 131072 && NT % 64 == 0;
+    static constexpr bool TWLDS = !TWREG && (LDSPF || cfg_twlds(FP64, M, KIND)) && M >= 8;
+    static constexpr bool PREFETCH = !LDSPF && cfg_prefetch(FP64, M, KIND) != 0;
+    static constexpr bool DEFER = cfg_defer(FP64, M, KIND) && (LDSPF || (PREFETCH && PF_FENCE));
+};
 
-    __shared__ cx<R> lds[C * M];
-    __shared__ double red[WAVES][5];
-    __shared__ double redg[RED_DEFER ? 2 : 1][RED_DEFER ? WAVES : 1][5];
+// The LDS of one pass kernel variant: the exchange tile, the group-sum
+// slots, the twiddle octant, the prefetch buffer, the one-sided partial sums
+// and the group's first fault.
+template <typename R, int M, int KIND, int FT, int NTHR = 0>
+struct PassShared {
+    using Cf = PassCfg<R, M, KIND, FT, NTHR>;
+    // 16-byte aligned: the LDS DMA writes 16 bytes per lane into nbuf
+    alignas(16) cx<R> lds[Cf::C * M];
+    alignas(16) cx<R> nbuf[Cf::LDSPF ? Cf::C * M : 1];
+    double red[Cf::WAVES][5];
+    double redg[Cf::RED_DEFER ? 2 : 1][Cf::RED_DEFER ? Cf::WAVES : 1][5];
+    cx<R> twl[Cf::TWLDS ? M / 8 + 1 : 1];
+    double redm[Cf::SIGM && KIND == KIND_STRIDED ? Cf::WAVES : 1][Cf::SIGM && KIND == KIND_STRIDED ? Cf::C : 1][3];
+    DevFault f0;
+};
 
-    const int tid = threadIdx.x;
+// Optional per-call hooks of pass_body: `slots` collects the record slots the
+// call appends (the persistent kernel corrects them before it releases the
+// item), at most `slot_cap` of them, counted in *n_slots.
+struct PassHooks {
+    int64_t *slots;
+    int *n_slots;
+    int slot_cap;
+};
+
+// The groups g_first, g_first + g_step, ... (< g_end) of one pass, processed
+// by one workgroup of PassCfg::NT threads with the LDS of `sh`.
+template <typename R, int M, int KIND, int FT, int NTHR>
+__device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KIND, FT, NTHR> &sh, int64_t g_first,
+                                          int64_t g_end, int64_t g_step, const PassHooks &hk) {
+    using Cf = PassCfg<R, M, KIND, FT, NTHR>;
+    constexpr int FP64 = Cf::FP64;
+    constexpr bool BLK = Cf::BLK, SIG = Cf::SIG, THR = Cf::THR;
+    constexpr bool PF_FENCE = Cf::PF_FENCE;
+    constexpr bool NT_ST = Cf::NT_ST;
+    constexpr bool ENC = Cf::ENC;
+    constexpr bool SIGR = Cf::SIGR;
+    constexpr bool SIGM = Cf::SIGM;
+    constexpr int E = Cf::E;
+    constexpr int T = Cf::T;
+    constexpr int C = Cf::C;
+    constexpr int NT = Cf::NT;
+    using St = Stages<M, E>;
+    constexpr int NSTAGE = St::count;
+    constexpr int WAVES = Cf::WAVES;
+    constexpr int WIDTH = Cf::WIDTH;
+    constexpr bool LDS_RED = Cf::LDS_RED;
+    constexpr bool RED_DEFER = Cf::RED_DEFER;
+
+    auto &lds = sh.lds;
+    auto &red = sh.red;
+    auto &redg = sh.redg;
+
+    int tid = threadIdx.x;
+    // persistent kernel: an opaque copy per call, so that what derives from
+    // the lane index is computed per item, not hoisted out of the item loop
+    // (every variant's lane constants would stay live across the whole loop)
+    if constexpr (NTHR > 0) asm volatile("" : "+v"(tid));
     int c, j;
     if constexpr (KIND == KIND_STRIDED) {
         c = tid % C;
@@ -568,16 +636,16 @@ pass_kernel(PassArgs a) {
     // Stage twiddles w_{NS*RAD}^{(i mod NS) q} (from the table of w_M^t) and
     // the pre-transform checksum vector at positions j + T m: either kept in
     // registers for all signals of the workgroup or re-read per signal.
-    constexpr bool TWREG = cfg_twreg(FP64, M, KIND) != 0;
-    constexpr bool CREG = ENC && cfg_creg(FP64, M, KIND) != 0;
+    constexpr bool TWREG = Cf::TWREG;
+    constexpr bool CREG = Cf::CREG;
     const cx<R> *stw = reinterpret_cast<const cx<R> *>(a.stw);
     const cx<double> *cv = reinterpret_cast<const cx<double> *>(a.cvec);
     // With the LDS prefetch, stage twiddles come from an LDS copy of the
     // first octant, w_M^t for t <= M/8, and the exact symmetries of the
     // table (the host builds it from the same octant): no global load in the
     // transform, whose wait would also wait for the prefetch.
-    constexpr bool TWLDS = !TWREG && (cfg_ldspf(FP64, M, KIND) != 0 || cfg_twlds(FP64, M, KIND)) && M >= 8;
-    __shared__ cx<R> twl[TWLDS ? M / 8 + 1 : 1];
+    constexpr bool TWLDS = Cf::TWLDS;
+    auto &twl = sh.twl;
     if constexpr (TWLDS) {
         for (int t = tid; t <= M / 8; t += NT) twl[t] = ldg(stw + t);
         __syncthreads();
@@ -621,13 +689,9 @@ pass_kernel(PassArgs a) {
     const double rotr = jr == 0 ? 1.0 : kW3r;
     const double roti = jr == 0 ? 0.0 : (jr == 1 ? kW3i : -kW3i);
 
-    const int nwg = gridDim.x;
-    int64_t wl = blockIdx.x;
-    if (nwg % 8 == 0) wl = (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;  // XCD-contiguous group ranges
-
     // FT_SIGNAL: a tile of C signals per iteration, each its own group (G = 1)
     const int rounds = SIGR ? 1 : a.G / C;
-    const int64_t n_iter = SIGR ? (a.n_groups + C - 1) / C : a.n_groups;
+    const int64_t n_iter = g_end;
     auto mloc = [&](int64_t gg, int rr) -> MemberLoc {
         if constexpr (SIGR) return member_loc<M, KIND, C>(a, gg * C + c, 0);
         else return member_loc<M, KIND, C>(a, gg, rr * C + c);
@@ -664,9 +728,9 @@ pass_kernel(PassArgs a) {
     // its own E elements of its own member; the instruction writes lane l of
     // a wavefront to slot base + l, so element m of thread tid goes to slot
     // m NT + tid, and a thread reads back only what its own lane wrote.
-    constexpr bool LDSPF = cfg_ldspf(FP64, M, KIND) != 0;
-    constexpr bool PREFETCH = !LDSPF && cfg_prefetch(FP64, M, KIND) != 0;
-    __shared__ cx<R> nbuf[LDSPF ? C * M : 1];
+    constexpr bool LDSPF = Cf::LDSPF;
+    constexpr bool PREFETCH = Cf::PREFETCH;
+    auto &nbuf = sh.nbuf;
     auto nslot = [&](int m) -> int { return tid + NT * m; };
     auto dma_tile = [&](int64_t gg, int rr) {
         if constexpr (LDSPF) {
@@ -684,13 +748,13 @@ pass_kernel(PassArgs a) {
             }
         }
     };
-    if constexpr (PREFETCH) load_tile(wl, 0);
-    if constexpr (LDSPF) dma_tile(wl, 0);
+    if constexpr (PREFETCH) load_tile(g_first, 0);
+    if constexpr (LDSPF) dma_tile(g_first, 0);
     // Deferred stores (LDS-prefetching row tiles): a tile's outputs stay in
     // registers and are stored right after the next tile's prefetch has been
     // waited for, so that the wait (which also counts stores) never waits
     // for stores issued just before it.
-    constexpr bool DEFER = cfg_defer(FP64, M, KIND) && (LDSPF || (PREFETCH && PF_FENCE));
+    constexpr bool DEFER = Cf::DEFER;
     cx<R> ps[DEFER ? E : 1];
     cx<R> *pdst = out;     // first element of the pending stores
     uint32_t pstr = 1;     // their stride
@@ -708,7 +772,7 @@ pass_kernel(PassArgs a) {
     // the member's residual and energy over its threads, test it against its
     // own threshold and record it (method: 1 for a one-signal group, 4 for a
     // sub-signal of a block tile, which the correction recomputes alone).
-    __shared__ double redm[SIGM && KIND == KIND_STRIDED ? WAVES : 1][SIGM && KIND == KIND_STRIDED ? C : 1][3];
+    auto &redm = sh.redm;
     auto member_check = [&](int64_t grp, int mem, bool valid, double d1r, double d1i, double ssum, int method) {
         double v[3] = {d1r, d1i, ssum};
         bool mine;  // this thread reports the member
@@ -761,6 +825,7 @@ pass_kernel(PassArgs a) {
                     DevRecord rc;
                     rc.group = a.g_base + grp;
                     rc.pass = a.pass;
+                    rc.task = a.task;
                     rc.action = 1;  // detected
                     rc.member = mem;
                     rc.method = method;
@@ -795,10 +860,12 @@ pass_kernel(PassArgs a) {
                 }
             }
             const unsigned long long slot = atomicAdd(&a.rep->n_flag, 1ULL);
+            if (hk.slots && *hk.n_slots < hk.slot_cap) hk.slots[(*hk.n_slots)++] = (int64_t)slot;
             if ((int64_t)slot < a.rec_cap) {
                 DevRecord rc;
                 rc.group = a.g_base + g;
                 rc.pass = a.pass;
+                rc.task = a.task;
                 rc.action = 1;  // detected
                 rc.member = jl;
                 rc.method = jl >= 0 ? 1 : 0;
@@ -814,7 +881,7 @@ pass_kernel(PassArgs a) {
     };
     int64_t g_prev = -1;  // RED_DEFER: the group whose decision is pending
     int it = 0;           // RED_DEFER: groups done by this workgroup
-    for (int64_t g = wl; g < n_iter; g += nwg) {
+    for (int64_t g = g_first; g < n_iter; g += g_step) {
         const int64_t gsig = g * C + c;  // FT_SIGNAL: this thread's signal (= its group)
         // the fault lookup reads a table entry or a constant -1 (no branch)
         const int32_t *fhp;
@@ -823,7 +890,7 @@ pass_kernel(PassArgs a) {
         const int fh = *fhp;
         // the group's first fault, staged in LDS once (fh is uniform outside
         // FT_SIGNAL, whose threads walk the list themselves)
-        __shared__ DevFault f0;
+        DevFault &f0 = sh.f0;
         bool fmulti = true;
         if constexpr (!SIGR) {
             if (fh >= 0) {
@@ -881,7 +948,7 @@ pass_kernel(PassArgs a) {
                 }
                 flush();
                 if (r + 1 < rounds) load_tile(g, r + 1);
-                else load_tile(g + nwg, 0);
+                else load_tile(g + g_step, 0);
             } else {
                 load_tile(g, r);
 #pragma unroll
@@ -913,7 +980,7 @@ pass_kernel(PassArgs a) {
             if constexpr (LDSPF) {
                 asm volatile("" ::: "memory");
                 if (r + 1 < rounds) dma_tile(g, r + 1);
-                else dma_tile(g + nwg, 0);
+                else dma_tile(g + g_step, 0);
             }
             if (a.conj_in) {
 #pragma unroll
@@ -1173,9 +1240,22 @@ pass_kernel(PassArgs a) {
     flush();
 }
 
-// ------------------------------------------------------- correction kernel
-constexpr int kCorrThreads = 256;
+template <typename R, int M, int KIND, int FT>
+__global__ void __launch_bounds__(cfg_threads(sizeof(R) == 8, M, KIND)) TFFT_PASS_OCCUPANCY
+pass_kernel(PassArgs a) {
+    using Cf = PassCfg<R, M, KIND, FT>;
+    __shared__ PassShared<R, M, KIND, FT> sh;
+    // XCD-contiguous group ranges: consecutive workgroups run on different
+    // XCDs, so workgroup b walks the groups of slot (b mod 8, b / 8)
+    const int nwg = gridDim.x;
+    int64_t wl = blockIdx.x;
+    if (nwg % 8 == 0) wl = (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
+    const int64_t n_iter = Cf::SIGR ? (a.n_groups + Cf::C - 1) / Cf::C : a.n_groups;
+    pass_body<R, M, KIND, FT, 0>(a, sh, wl, n_iter, nwg, PassHooks{nullptr, nullptr, 0});
+}
 
+// ------------------------------------------------------- correction kernel
+template <int NTH>
 __device__ __forceinline__ double block_sum(double v, double *scratch) {
     v = wave_sum(v, 64);
     const int tid = threadIdx.x;
@@ -1184,30 +1264,30 @@ __device__ __forceinline__ double block_sum(double v, double *scratch) {
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < kCorrThreads / 64; ++w) t += scratch[w];
+    for (int w = 0; w < NTH / 64; ++w) t += scratch[w];
     return t;
 }
 
-template <typename R, int M, int KIND>
-__global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
-    constexpr int FP64 = sizeof(R) == 8;
-    constexpr int C = cfg_C(FP64, M, KIND);
-    __shared__ cx<double> buf[M];  // the binary64 transform, in place
-    __shared__ double scratch[kCorrThreads / 64];
-    const int tid = threadIdx.x;
+// Correction of record i (a flagged group of the pass described by `a`) by
+// one workgroup of NTH threads, with C the tile width of the pass kernel that
+// defined the group layout; `buf` holds M binary64 values, `scratch` NTH / 64
+// doubles (LDS).  Records of another pass, task or chunk, or already acted
+// on, are skipped.
+template <typename R, int M, int KIND, int C, int NTH>
+__device__ __forceinline__ void correct_record(const PassArgs &a, int64_t i, cx<double> *buf, double *scratch) {
+    constexpr int kCorrThreads = NTH;
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));  // per call (see pass_body)
     const cx<R> *in = reinterpret_cast<const cx<R> *>(a.in);
     cx<R> *out = reinterpret_cast<cx<R> *>(a.out);
     const cx<double> *cv = reinterpret_cast<const cx<double> *>(a.cvec);
     const cx<double> *w64 = reinterpret_cast<const cx<double> *>(a.stw64);
-
-    unsigned long long nrec = a.rep->n_flag;
-    if ((int64_t)nrec > a.rec_cap) nrec = a.rec_cap;
-    for (int64_t i = blockIdx.x; i < (int64_t)nrec; i += gridDim.x) {
+    {
         const DevRecord rec = a.recs[i];
         // records of this pass and of this launch's groups (a chunk of the
         // batch covers groups g_base .. g_base + n_groups - 1)
-        if (rec.pass != a.pass || rec.action != 1) continue;
-        if (rec.group < a.g_base || rec.group >= a.g_base + a.n_groups) continue;
+        if (rec.pass != a.pass || rec.task != a.task || rec.action != 1) return;
+        if (rec.group < a.g_base || rec.group >= a.g_base + a.n_groups) return;
         const int64_t g = rec.group - a.g_base;
 
         // applied output twiddle of member loc at output k (1 outside strided passes)
@@ -1257,9 +1337,9 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
                     dr += e.re * y.re - e.im * y.im;
                     di += e.re * y.im + e.im * y.re;
                 }
-                dr = block_sum(dr, scratch);
-                di = block_sum(di, scratch);
-                sb = block_sum(sb, scratch);
+                dr = block_sum<NTH>(dr, scratch);
+                di = block_sum<NTH>(di, scratch);
+                sb = block_sum<NTH>(sb, scratch);
                 const double taub = a.tau_coef * sqrt(sb);
                 if (!(sqrt(dr * dr + di * di) <= taub)) {
                     ++ncand;
@@ -1379,7 +1459,7 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
                 const cx<double> v = buf[kk];
                 nrm += v.re * v.re + v.im * v.im;
             }
-            nrm = block_sum(nrm, scratch);
+            nrm = block_sum<NTH>(nrm, scratch);
             action = (sqrt(nrm) <= rec.tau) ? 3 : 4;
         }
         if (tid == 0) {
@@ -1390,6 +1470,19 @@ __global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
         }
         __syncthreads();
     }
+}
+
+constexpr int kCorrThreads = 256;
+
+template <typename R, int M, int KIND>
+__global__ void __launch_bounds__(kCorrThreads) correct_kernel(PassArgs a) {
+    constexpr int C = cfg_C(sizeof(R) == 8, M, KIND);
+    __shared__ cx<double> buf[M];  // the binary64 transform, in place
+    __shared__ double scratch[kCorrThreads / 64];
+    unsigned long long nrec = a.rep->n_flag;
+    if ((int64_t)nrec > a.rec_cap) nrec = a.rec_cap;
+    for (int64_t i = blockIdx.x; i < (int64_t)nrec; i += gridDim.x)
+        correct_record<R, M, KIND, C, kCorrThreads>(a, i, buf, scratch);
 }
 
 // ------------------------------------------------------------- dispatch

@@ -20,6 +20,7 @@
 using namespace tfft;
 using cd = std::complex<double>;
 
+
 static_assert(kScratchBytes == TFFT_SCRATCH_BYTES, "static scratch size as declared in the header");
 
 namespace {
@@ -107,6 +108,7 @@ struct tfft_plan_s {
     hipEvent_t ev[2 * kMaxPasses + 1] = {};
     int launched_correct = 0;
     int64_t chunk = 0;           // multi-pass plans: signals per chunk of the batch (= batch: no chunking)
+    int persistent = 0;          // shaped for the persistent ragged kernel (tiles of 512 threads)
 };
 
 namespace {
@@ -167,7 +169,8 @@ int shape_pass(tfft_plan_s *p, int idx, int M, int kind, int Guser, int grid_sca
     P.M = M;
     P.kind = kind;
     P.E = cfg_E(fp64, M, kind);
-    P.C = cfg_C(fp64, M, kind);
+    // the persistent kernel widens every tile to 512 threads (PassCfg with NTHR = 512)
+    P.C = p->persistent ? std::max(1, kPersistThreads / (M / P.E)) : cfg_C(fp64, M, kind);
     P.stages = n_stages(M, P.E);
     const int G0 = Guser > 0 ? Guser : (kind == KIND_ROWS ? default_group(M) : 64);
     int64_t tiles;  // workgroup iterations of the pass
@@ -343,6 +346,73 @@ ChunkGeom chunk_geom(const tfft_plan_s *p, const PassPlan &P, int64_t c0, int64_
     return c;
 }
 
+// Arguments of the launch of pass i over the signals described by cg (nb
+// signals from cin / cout, the caller's buffers from the chunk's first
+// signal, or the ragged offset table sig), with the plan's tables and the
+// given report buffers.
+PassArgs pass_args(const tfft_plan_s *p, int i, const ChunkGeom &cg, int64_t nb, const void *cin, void *cout,
+                   void *work, const int64_t *sig, bool inverse, int mode, DevReport *rep, DevRecord *recs) {
+    PassArgs A;
+    std::memset(&A, 0, sizeof(A));
+    const PassPlan &P = p->pass[i];
+    const bool last = i == p->passes - 1;
+    const int fp64 = p->dtype == TFFT_C128;
+    // every pass reads a buffer it does not write, so a flagged group can
+    // re-read its inputs: 1 pass in->out; 2 passes in->work->out;
+    // 3 passes in->out->work->out (out holds the pass-1 result meanwhile)
+    if (p->passes == 1) {
+        A.in = cin;
+        A.out = cout;
+    } else if (p->passes == 2) {
+        A.in = i == 0 ? cin : work;
+        A.out = i == 0 ? work : cout;
+    } else {
+        A.in = i == 0 ? cin : (i == 1 ? (const void *)cout : work);
+        A.out = i == 1 ? work : cout;
+    }
+    A.batch = nb;
+    A.n = p->n;
+    A.L = P.L;
+    A.S = P.S;
+    A.O = P.O;
+    A.rows = P.rows;
+    A.m1 = P.m1;
+    A.m2 = P.m2;
+    A.tw_scale = P.tw_scale;
+    A.n_outer = cg.n_outer;
+    // ragged classes address their signals through the offset table in
+    // the user buffers; the workspace is always dense [chunk][n]
+    A.in_sig = (A.in == cin || A.in == (const void *)cout) ? sig : nullptr;
+    A.out_sig = (A.out == cout) ? sig : nullptr;
+    A.G = P.G;
+    A.rb = P.rb;
+    A.n_strips = P.n_strips;
+    A.m1_log2 = ilog2_64(P.m1);
+    A.ns_log2 = ilog2_64(P.n_strips);
+    A.o_log2 = ilog2_64(P.O);
+    A.n_groups = cg.n_groups;
+    A.g_base = cg.g_base;
+    A.conj_in = inverse ? 1 : 0;
+    A.conj_out = inverse ? 1 : 0;
+    A.out_scale = (inverse && last && !(p->flags & TFFT_INVERSE_UNSCALED)) ? 1.0 / (double)p->n : 1.0;
+    A.cvec = !inverse ? P.d_cfwd : ((p->flags & TFFT_INVERSE_UNSCALED) ? P.d_cinv_unscaled : P.d_cinv);
+    A.stw = P.d_stw;
+    A.stw64 = P.d_stw64;
+    A.itw_lo = p->d_itw_lo;
+    A.itw_hi = p->d_itw_hi;
+    A.itw_bits = p->itw_bits;
+    A.pass = i;
+    A.tau_coef = P.tau_coef * A.out_scale;  // the outputs' rounding noise scales with them
+    A.rep = rep;
+    A.recs = recs;
+    A.rec_cap = p->rec_cap;
+    A.fault_head = P.d_fault_head;
+    A.faults = P.d_faults;
+    A.kappa_u = p->kappa * (fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
+    A.fix = mode == TFFT_FT_CORRECT;
+    return A;
+}
+
 // Device buffers of one execution: the report counters, the records and the
 // multi-pass workspace (the plan's own, or parts of the static scratch).
 struct ExecBufs {
@@ -396,61 +466,8 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
         const int64_t *sig = p->d_sig_off ? p->d_sig_off + c0 : nullptr;
         for (int i = 0; i < p->passes; ++i) {
             const PassPlan &P = p->pass[i];
-            const bool last = i == p->passes - 1;
             const ChunkGeom cg = chunk_geom(p, P, c0, nb);
-            PassArgs A;
-            std::memset(&A, 0, sizeof(A));
-            // every pass reads a buffer it does not write, so a flagged group can
-            // re-read its inputs: 1 pass in->out; 2 passes in->work->out;
-            // 3 passes in->out->work->out (out holds the pass-1 result meanwhile)
-            if (p->passes == 1) {
-                A.in = cin;
-                A.out = cout;
-            } else if (p->passes == 2) {
-                A.in = i == 0 ? cin : work;
-                A.out = i == 0 ? work : cout;
-            } else {
-                A.in = i == 0 ? cin : (i == 1 ? (const void *)cout : work);
-                A.out = i == 1 ? work : cout;
-            }
-            A.batch = nb;
-            A.n = p->n;
-            A.L = P.L;
-            A.S = P.S;
-            A.O = P.O;
-            A.rows = P.rows;
-            A.m1 = P.m1;
-            A.m2 = P.m2;
-            A.tw_scale = P.tw_scale;
-            A.n_outer = cg.n_outer;
-            // ragged classes address their signals through the offset table in
-            // the user buffers; the workspace is always dense [chunk][n]
-            A.in_sig = (A.in == cin || A.in == (const void *)cout) ? sig : nullptr;
-            A.out_sig = (A.out == cout) ? sig : nullptr;
-            A.G = P.G;
-            A.rb = P.rb;
-            A.n_strips = P.n_strips;
-            A.m1_log2 = ilog2_64(P.m1);
-            A.n_groups = cg.n_groups;
-            A.g_base = cg.g_base;
-            A.conj_in = inverse ? 1 : 0;
-            A.conj_out = inverse ? 1 : 0;
-            A.out_scale = (inverse && last && !(p->flags & TFFT_INVERSE_UNSCALED)) ? 1.0 / (double)p->n : 1.0;
-            A.cvec = !inverse ? P.d_cfwd : ((p->flags & TFFT_INVERSE_UNSCALED) ? P.d_cinv_unscaled : P.d_cinv);
-            A.stw = P.d_stw;
-            A.stw64 = P.d_stw64;
-            A.itw_lo = p->d_itw_lo;
-            A.itw_hi = p->d_itw_hi;
-            A.itw_bits = p->itw_bits;
-            A.pass = i;
-            A.tau_coef = P.tau_coef * A.out_scale;  // the outputs' rounding noise scales with them
-            A.rep = rep;
-            A.recs = recs;
-            A.rec_cap = p->rec_cap;
-            A.fault_head = P.d_fault_head;
-            A.faults = P.d_faults;
-            A.kappa_u = p->kappa * (fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
-            A.fix = mode == TFFT_FT_CORRECT;
+            const PassArgs A = pass_args(p, i, cg, nb, cin, cout, work, sig, inverse, mode, rep, recs);
             if (launch_pass(fp64, P.M, P.kind, scheme_ft, A, cg.grid, st) != hipSuccess) return TFFT_E_HIP;
             if (per_pass_events && hipEventRecord(p->ev[1 + 2 * i], st) != hipSuccess) return TFFT_E_HIP;
             if (correct) {
@@ -478,6 +495,14 @@ int exec(tfft_plan_s *p, const void *d_in, void *d_out, int mode, void *stream, 
 extern "C" {
 
 int tfft_version(void) { return TFFT_VERSION; }
+
+int tfft_stream_copy(void *d_dst, const void *d_src, size_t bytes, void *hip_stream) {
+    if (!d_dst || !d_src || (((uintptr_t)d_dst | (uintptr_t)d_src) & 15)) return TFFT_E_INVALID;
+    const uintptr_t a = (uintptr_t)d_src, b = (uintptr_t)d_dst;
+    if ((a < b ? b - a : a - b) < bytes) return TFFT_E_INVALID;  // overlapping
+    if (bytes == 0) return TFFT_OK;
+    return launch_stream_copy(d_dst, d_src, bytes, (hipStream_t)hip_stream) == hipSuccess ? TFFT_OK : TFFT_E_HIP;
+}
 
 const char *tfft_status_string(int s) {
     switch (s) {
@@ -508,7 +533,10 @@ int shape_plan(tfft_plan_s *p, int64_t n, int64_t batch, int dtype, const tfft_o
     const int Guser = opt ? opt->group : 0;
     if (Guser < 0 || Guser > 64 || (Guser & (Guser - 1)) != 0) return TFFT_E_INVALID;
     if (opt && (opt->kappa < 0 || !std::isfinite(opt->kappa))) return TFFT_E_INVALID;
-    if (flags & ~(uint32_t)TFFT_INVERSE_UNSCALED) return TFFT_E_INVALID;
+    if (flags & ~(uint32_t)(TFFT_INVERSE_UNSCALED | TFFT_PERSISTENT)) return TFFT_E_INVALID;
+    if ((flags & TFFT_PERSISTENT) && !ragged) return TFFT_E_INVALID;  // a ragged-batch mode
+    const int split = opt ? opt->split : 0;
+    if (split < 0 || split > 1) return TFFT_E_INVALID;
     const int force_passes = opt ? opt->passes : 0;
     const int grid_scale = opt ? opt->grid_scale : 0;
     const int scheme = opt ? opt->scheme : TFFT_SCHEME_BLOCK;
@@ -526,6 +554,7 @@ int shape_plan(tfft_plan_s *p, int64_t n, int64_t batch, int dtype, const tfft_o
     p->flags = flags;
     p->kappa = (opt && opt->kappa > 0) ? opt->kappa : (dtype == TFFT_C128 ? TFFT_KAPPA64 : TFFT_KAPPA32);
     p->scheme = scheme;
+    p->persistent = (flags & TFFT_PERSISTENT) ? 1 : 0;
     // one pass up to 2^13 (the paper's single-launch limit); two passes up to
     // 2^19 (complex64) / 2^20; three passes above, the shortest first (tiles
     // of the strided passes then hold >= 16 adjacent sub-signals, i.e.
@@ -542,15 +571,23 @@ int shape_plan(tfft_plan_s *p, int64_t n, int64_t batch, int dtype, const tfft_o
         p->passes = 1;
         p->lens[0] = (int)n;
     } else if (npass == 2) {
+        // split 1: the longer sub-transform first
         p->passes = 2;
-        p->lens[0] = 1 << (k / 2);
-        p->lens[1] = 1 << (k - k / 2);
+        p->lens[split ? 1 : 0] = 1 << (k / 2);
+        p->lens[split ? 0 : 1] = 1 << (k - k / 2);
     } else {
+        // split 1: the middle length first
         p->passes = 3;
         const int a = k / 3, b = (k - a) / 2, c = k - a - b;
-        p->lens[0] = 1 << a;
-        p->lens[1] = 1 << b;
+        p->lens[0] = 1 << (split ? b : a);
+        p->lens[1] = 1 << (split ? a : b);
         p->lens[2] = 1 << c;
+    }
+    if (p->persistent) {
+        // the persistent kernel's variants: rows of 64..4096 points, strided
+        // and last passes of 64..1024 points
+        for (int i = 0; i < p->passes; ++i)
+            if (p->lens[i] < 64 || p->lens[i] > (p->passes == 1 ? 4096 : 1024)) return TFFT_E_UNSUPPORTED;
     }
     for (int i = 0; i < p->passes; ++i) {
         const int kind = p->passes == 1 ? KIND_ROWS : (i == p->passes - 1 ? KIND_LAST : KIND_STRIDED);
@@ -629,6 +666,44 @@ int create_plan(tfft_plan *out, int64_t n, int64_t batch, int dtype, const tfft_
     return TFFT_OK;
 }
 
+// A device record as the caller sees it: the group's member mapped back to
+// (signal, sub-transform), the residual, threshold and quotient.
+tfft_record host_record(const tfft_plan_s *p, const DevRecord &d) {
+    tfft_record r;
+    std::memset(&r, 0, sizeof(r));
+    const bool pass_ok = d.pass >= 0 && d.pass < p->passes;
+    const PassPlan &P = p->pass[pass_ok ? d.pass : 0];
+    // a member outside the group (never written by the kernels) reads as
+    // the group's first signal
+    const int mem = (d.member >= 0 && d.member < P.G) ? d.member : 0;
+    if (P.kind == KIND_ROWS) {
+        r.signal = d.group * P.G + mem;
+        r.sub = d.method == TFFT_LOC_THREAD ? (int64_t)d.s : 0;
+    } else {
+        const int64_t strip = d.group % P.n_strips, ublk = d.group / P.n_strips;
+        const int64_t u = ublk * P.rb + mem / P.C, i2 = strip * P.C + mem % P.C;
+        if (P.kind == KIND_STRIDED) {
+            r.signal = u / P.O;
+            r.sub = (u % P.O) * P.S + i2;
+        } else {
+            r.signal = u;
+            r.sub = i2;
+        }
+    }
+    if (r.signal < 0 || r.signal >= p->batch) r.signal = std::min<int64_t>(p->batch - 1, std::max<int64_t>(0, r.signal));
+    r.group = d.group;
+    r.pass = d.pass;
+    r.member = d.member;
+    r.action = d.action;
+    r.method = d.method;
+    r.residual = std::sqrt(d.d1r * d.d1r + d.d1i * d.d1i);
+    r.threshold = d.tau;
+    const double den = d.d1r * d.d1r + d.d1i * d.d1i;
+    r.ratio_re = (d.d2r * d.d1r + d.d2i * d.d1i) / den;
+    r.ratio_im = (d.d2i * d.d1r - d.d2r * d.d1i) / den;
+    return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -702,41 +777,7 @@ int tfft_get_report(tfft_plan p, tfft_counts *counts, tfft_record *recs, int64_t
         counts->dropped = (int64_t)h.n_flag - nrec;
     }
     std::vector<tfft_record> out((size_t)nrec);
-    for (int64_t i = 0; i < nrec; ++i) {
-        const DevRecord &d = dr[(size_t)i];
-        tfft_record &r = out[(size_t)i];
-        std::memset(&r, 0, sizeof(r));
-        const bool pass_ok = d.pass >= 0 && d.pass < p->passes;
-        const PassPlan &P = p->pass[pass_ok ? d.pass : 0];
-        // a member outside the group (never written by the kernels) reads as
-        // the group's first signal
-        const int mem = (d.member >= 0 && d.member < P.G) ? d.member : 0;
-        if (P.kind == KIND_ROWS) {
-            r.signal = d.group * P.G + mem;
-            r.sub = d.method == TFFT_LOC_THREAD ? (int64_t)d.s : 0;
-        } else {
-            const int64_t strip = d.group % P.n_strips, ublk = d.group / P.n_strips;
-            const int64_t u = ublk * P.rb + mem / P.C, i2 = strip * P.C + mem % P.C;
-            if (P.kind == KIND_STRIDED) {
-                r.signal = u / P.O;
-                r.sub = (u % P.O) * P.S + i2;
-            } else {
-                r.signal = u;
-                r.sub = i2;
-            }
-        }
-        if (r.signal < 0 || r.signal >= p->batch) r.signal = std::min<int64_t>(p->batch - 1, std::max<int64_t>(0, r.signal));
-        r.group = d.group;
-        r.pass = d.pass;
-        r.member = d.member;
-        r.action = d.action;
-        r.method = d.method;
-        r.residual = std::sqrt(d.d1r * d.d1r + d.d1i * d.d1i);
-        r.threshold = d.tau;
-        const double den = d.d1r * d.d1r + d.d1i * d.d1i;
-        r.ratio_re = (d.d2r * d.d1r + d.d2i * d.d1i) / den;
-        r.ratio_im = (d.d2i * d.d1r - d.d2r * d.d1i) / den;
-    }
+    for (int64_t i = 0; i < nrec; ++i) out[(size_t)i] = host_record(p, dr[(size_t)i]);
     // deterministic order whatever the order the device wrote them in
     std::sort(out.begin(), out.end(), [](const tfft_record &x, const tfft_record &y) {
         if (x.signal != y.signal) return x.signal < y.signal;
@@ -898,6 +939,25 @@ struct tfft_ragged_s {
     hipEvent_t ev_fork = nullptr, ev_join[TFFT_GRAPH_BRANCHES] = {};
     std::vector<int> branch_of;  // class -> branch
     std::vector<std::vector<tfft_fault>> class_faults;  // installed faults per class (class-local signals)
+
+    // persistent execution (TFFT_PERSISTENT): one kernel drains a queue of
+    // work items covering every pass of every class
+    int persistent = 0;
+    int64_t item_bytes = 0;               // target bytes moved per work item (0: default)
+    std::vector<int> task_class, task_pass;
+    std::vector<PItem> h_items;
+    int n_done = 0;                       // release counters: one per (task, chunk)
+    PItem *d_items = nullptr;
+    PTask *d_tasks = nullptr;
+    int32_t *d_need = nullptr, *d_done = nullptr, *d_err = nullptr;
+    unsigned long long *d_head = nullptr;
+    DevReport *d_rep = nullptr;           // one report for all classes
+    DevRecord *d_recs = nullptr;
+    int64_t rec_cap = 0;
+    int tasks_valid = 0;                  // d_tasks holds the tables for this key:
+    const void *t_in = nullptr;
+    void *t_out = nullptr;
+    int t_mode = -1, t_inv = -1;
 };
 
 namespace {
@@ -978,6 +1038,249 @@ int ragged_launch_branches(tfft_ragged_s *r, const void *d_in, void *d_out, int 
     return rc;
 }
 
+constexpr int64_t kPChunk = 64;                 // signals per dependency chunk
+constexpr int64_t kPItemBytes = int64_t(4) << 20;  // default bytes moved per work item
+
+void persist_free(tfft_ragged_s *r) {
+    (void)hipFree(r->d_items);
+    (void)hipFree(r->d_tasks);
+    (void)hipFree(r->d_need);
+    (void)hipFree(r->d_done);
+    (void)hipFree(r->d_err);
+    (void)hipFree(r->d_head);
+    (void)hipFree(r->d_rep);
+    (void)hipFree(r->d_recs);
+    r->d_items = nullptr;
+    r->d_tasks = nullptr;
+    r->d_need = r->d_done = r->d_err = nullptr;
+    r->d_head = nullptr;
+    r->d_rep = nullptr;
+    r->d_recs = nullptr;
+    r->tasks_valid = 0;
+}
+
+// The work queue of a persistent ragged plan from its class plans: tasks
+// (class, pass), chunks of 64 signals per class, items of up to kPSlotCap
+// groups (about item_bytes moved each), and the items per (task, chunk) that
+// a later pass waits for.  Queue order: every multi-pass class's pass 0, then
+// pass 1, then pass 2 (larger classes first within a level), then the
+// one-pass classes, whose items need nothing and fill the end.
+int persist_build(tfft_ragged_s *r) {
+    persist_free(r);
+    r->task_class.clear();
+    r->task_pass.clear();
+    const size_t nc = r->classes.size();
+    std::vector<int> task0(nc);
+    for (size_t c = 0; c < nc; ++c) {
+        task0[c] = (int)r->task_class.size();
+        for (int i = 0; i < r->classes[c].plan->passes; ++i) {
+            r->task_class.push_back((int)c);
+            r->task_pass.push_back(i);
+        }
+    }
+    const int ntask = (int)r->task_class.size();
+    std::vector<int> done_base(ntask);
+    int nd = 0;
+    for (int t = 0; t < ntask; ++t) {
+        done_base[t] = nd;
+        nd += (int)((r->classes[(size_t)r->task_class[t]].plan->batch + kPChunk - 1) / kPChunk);
+    }
+    r->n_done = nd;
+    std::vector<int32_t> need((size_t)std::max(1, nd), 0);
+    const int64_t target = r->item_bytes > 0 ? r->item_bytes : kPItemBytes;
+    // items per task, in chunk order
+    std::vector<std::vector<PItem>> per(ntask);
+    for (int t = 0; t < ntask; ++t) {
+        const tfft_plan_s *p = r->classes[(size_t)r->task_class[t]].plan;
+        const PassPlan &P = p->pass[r->task_pass[t]];
+        const size_t esz = p->dtype == TFFT_C128 ? 16 : 8;
+        const int64_t gbytes = 2 * (int64_t)P.G * P.M * (int64_t)esz;
+        const int64_t K = std::max<int64_t>(1, std::min<int64_t>(kPSlotCap, target / std::max<int64_t>(1, gbytes)));
+        for (int64_t q = 0; q * kPChunk < p->batch; ++q) {
+            const ChunkGeom cg = chunk_geom(p, P, q * kPChunk, std::min(kPChunk, p->batch - q * kPChunk));
+            for (int64_t g = cg.g_base; g < cg.g_base + cg.n_groups; g += K) {
+                PItem it;
+                it.task = t;
+                it.chunk = (int32_t)q;
+                it.g0 = g;
+                it.g1 = std::min(g + K, cg.g_base + cg.n_groups);
+                per[t].push_back(it);
+                ++need[(size_t)(done_base[t] + q)];
+            }
+        }
+    }
+    // classes by bytes, largest first
+    std::vector<size_t> order(nc);
+    for (size_t c = 0; c < nc; ++c) order[c] = c;
+    auto bytes = [&](size_t c) { return r->classes[c].n * (int64_t)r->classes[c].members.size(); };
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return bytes(a) > bytes(b); });
+    r->h_items.clear();
+    for (int level = 0; level < kMaxPasses; ++level)
+        for (size_t c : order)
+            if (r->classes[c].plan->passes > 1 && level < r->classes[c].plan->passes)
+                for (const PItem &it : per[(size_t)(task0[c] + level)]) r->h_items.push_back(it);
+    for (size_t c : order)
+        if (r->classes[c].plan->passes == 1)
+            for (const PItem &it : per[(size_t)task0[c]]) r->h_items.push_back(it);
+    r->rec_cap = 0;
+    for (auto &C : r->classes) r->rec_cap += C.plan->rec_cap;
+    int rc = upload(&r->d_items, r->h_items);
+    if (rc == TFFT_OK) rc = upload(&r->d_need, need);
+    if (rc == TFFT_OK && (hipMalloc((void **)&r->d_tasks, sizeof(PTask) * (size_t)std::max(1, ntask)) != hipSuccess ||
+                          hipMalloc((void **)&r->d_done, sizeof(int32_t) * (size_t)std::max(1, nd)) != hipSuccess ||
+                          hipMalloc((void **)&r->d_err, sizeof(int32_t)) != hipSuccess ||
+                          hipMalloc((void **)&r->d_head, sizeof(unsigned long long)) != hipSuccess ||
+                          hipMalloc((void **)&r->d_rep, sizeof(DevReport)) != hipSuccess ||
+                          hipMalloc((void **)&r->d_recs, sizeof(DevRecord) * (size_t)r->rec_cap) != hipSuccess))
+        rc = TFFT_E_NOMEM;
+    if (rc != TFFT_OK) persist_free(r);
+    return rc;
+}
+
+// The task table for one execution (buffers, direction, mode), uploaded when
+// any of them changed (a synchronous copy: never under stream capture).
+int persist_tasks(tfft_ragged_s *r, const void *d_in, void *d_out, int mode, int inverse) {
+    if (r->tasks_valid && r->t_in == d_in && r->t_out == d_out && r->t_mode == mode && r->t_inv == inverse)
+        return TFFT_OK;
+    const int ntask = (int)r->task_class.size();
+    std::vector<PTask> tasks((size_t)ntask);
+    int nd = 0;
+    for (int t = 0; t < ntask; ++t) {
+        const tfft_plan_s *p = r->classes[(size_t)r->task_class[t]].plan;
+        const int i = r->task_pass[t];
+        const ChunkGeom cg = chunk_geom(p, p->pass[i], 0, p->batch);
+        PTask &k = tasks[(size_t)t];
+        std::memset(&k, 0, sizeof(k));
+        k.a = pass_args(p, i, cg, p->batch, d_in, d_out, p->d_work, p->d_sig_off, inverse != 0, mode, r->d_rep,
+                        r->d_recs);
+        k.a.rec_cap = r->rec_cap;
+        k.a.task = t;
+        k.variant = pvariant_id(p->pass[i].kind, p->pass[i].M);
+        k.dep = i > 0 ? t - 1 : -1;
+        k.done_base = nd;
+        k.fix = mode == TFFT_FT_CORRECT;
+        nd += (int)((p->batch + kPChunk - 1) / kPChunk);
+    }
+    if (hipMemcpy(r->d_tasks, tasks.data(), sizeof(PTask) * (size_t)ntask, hipMemcpyHostToDevice) != hipSuccess)
+        return TFFT_E_HIP;
+    r->tasks_valid = 1;
+    r->t_in = d_in;
+    r->t_out = d_out;
+    r->t_mode = mode;
+    r->t_inv = inverse;
+    return TFFT_OK;
+}
+
+// One persistent execution on st: the queue reset and the kernel.
+int persist_launch_all(tfft_ragged_s *r, int mode, hipStream_t st) {
+    PQueue q;
+    q.items = r->d_items;
+    q.n_items = (int64_t)r->h_items.size();
+    q.tasks = r->d_tasks;
+    q.head = r->d_head;
+    q.done = r->d_done;
+    q.need = r->d_need;
+    q.err = r->d_err;
+    q.spin_limit = int64_t(1) << 21;  // a few seconds of polls at most
+    const int fp64 = r->dtype == TFFT_C128, ft = mode != TFFT_FT_OFF;
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, r->device);
+    const int occ = std::max(1, persist_occupancy(fp64, ft));
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(q.n_items, (int64_t)occ * std::max(1, cus)));
+    if (launch_persist_reset(q, r->n_done, r->d_rep, st) != hipSuccess) return TFFT_E_HIP;
+    if (launch_persist(fp64, ft, q, grid, st) != hipSuccess) return TFFT_E_HIP;
+    return TFFT_OK;
+}
+
+// Autotuner of a persistent ragged plan: coordinate descent over the
+// classes (largest first) on the time of the whole persistent execution
+// (FT CORRECT on the caller's buffers): per class the pass count, the split
+// of the stages over the passes and the checksum group size (one-pass classes
+// keep one pass), then the bytes per work item.
+int persist_tune(tfft_ragged_s *r, const void *d_in, void *d_out, hipStream_t st, int reps) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TFFT_E_HIP;
+    auto time_all = [&](float *ms) -> int {
+        drop_graph(r);
+        int rc = persist_tasks(r, d_in, d_out, TFFT_FT_CORRECT, 0);
+        for (int t = 0; t <= reps && rc == TFFT_OK; ++t) {  // the first run warms up
+            if (t == 1 && hipEventRecord(e0, st) != hipSuccess) rc = TFFT_E_HIP;
+            if (rc == TFFT_OK) rc = persist_launch_all(r, TFFT_FT_CORRECT, st);
+        }
+        if (rc == TFFT_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+            rc = TFFT_E_HIP;
+        return rc;
+    };
+    std::vector<tfft_options> cur(r->classes.size(), r->opt);
+    float best = 0.f;
+    int status = time_all(&best);
+    std::vector<size_t> order(r->classes.size());
+    for (size_t c = 0; c < order.size(); ++c) order[c] = c;
+    auto bytes = [&](size_t c) { return r->classes[c].n * (int64_t)r->classes[c].members.size(); };
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return bytes(a) > bytes(b); });
+    for (size_t ci : order) {
+        if (status != TFFT_OK) break;
+        const int k = ilog2_64(r->classes[ci].n);
+        std::vector<tfft_options> cand;
+        if (k <= TFFT_ONE_PASS_MAX_LOG2) {
+            for (int grp : {0, 16, 32, 64}) {
+                tfft_options o = r->opt;
+                o.passes = 1;
+                o.group = grp;
+                cand.push_back(o);
+            }
+        } else {
+            for (int ps = 2; ps <= 3; ++ps)
+                for (int sp = 0; sp <= 1; ++sp)
+                    for (int grp : {0, 16}) {
+                        if ((ps == 2 && k > 20) || (ps == 3 && k < 12)) continue;
+                        tfft_options o = r->opt;
+                        o.passes = ps;
+                        o.split = sp;
+                        o.group = grp;
+                        cand.push_back(o);
+                    }
+        }
+        tfft_options best_o = cur[ci];
+        for (const auto &o : cand) {
+            if (build_class(r, ci, o) != TFFT_OK) continue;  // unsupported candidate
+            float ms = 0.f;
+            if (persist_build(r) != TFFT_OK || time_all(&ms) != TFFT_OK) continue;
+            if (ms < best) {
+                best = ms;
+                best_o = o;
+            }
+        }
+        cur[ci] = best_o;
+        status = build_class(r, ci, best_o);
+        if (status == TFFT_OK) status = persist_build(r);
+    }
+    // bytes moved per work item
+    int64_t best_ib = r->item_bytes;
+    for (int64_t ib : {int64_t(1) << 20, int64_t(2) << 20, int64_t(4) << 20, int64_t(8) << 20}) {
+        if (status != TFFT_OK) break;
+        r->item_bytes = ib;
+        float ms = 0.f;
+        if (persist_build(r) == TFFT_OK && time_all(&ms) == TFFT_OK && ms < best) {
+            best = ms;
+            best_ib = ib;
+        }
+    }
+    r->item_bytes = best_ib;
+    if (status == TFFT_OK) status = persist_build(r);
+    // the new class plans get the faults installed on the old ones
+    for (size_t ci = 0; ci < r->classes.size() && status == TFFT_OK; ++ci)
+        if (ci < r->class_faults.size() && !r->class_faults[ci].empty())
+            status = tfft_set_faults(r->classes[ci].plan, r->class_faults[ci].data(),
+                                     (int64_t)r->class_faults[ci].size());
+    r->tasks_valid = 0;
+    drop_graph(r);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1021,8 +1324,16 @@ int tfft_ragged_create(tfft_ragged *out, int64_t count, const int64_t *lengths, 
         r->local_of[(size_t)i] = (int64_t)r->classes[c].members.size();
         r->classes[c].members.push_back(i);
     }
+    r->persistent = (r->opt.flags & TFFT_PERSISTENT) ? 1 : 0;
     for (size_t c = 0; c < r->classes.size(); ++c) {
         const int rc = build_class(r, c, r->opt);
+        if (rc != TFFT_OK) {
+            tfft_ragged_destroy(r);
+            return rc;
+        }
+    }
+    if (r->persistent) {
+        const int rc = persist_build(r);
         if (rc != TFFT_OK) {
             tfft_ragged_destroy(r);
             return rc;
@@ -1036,6 +1347,7 @@ int tfft_ragged_destroy(tfft_ragged r) {
     if (!r) return TFFT_OK;
     Guard guard(r->device);
     drop_graph(r);
+    persist_free(r);
     for (auto &C : r->classes) tfft_plan_destroy(C.plan);
     for (int b = 0; b < TFFT_GRAPH_BRANCHES; ++b) {
         if (r->aux[b]) (void)hipStreamDestroy(r->aux[b]);
@@ -1053,6 +1365,47 @@ int tfft_ragged_exec(tfft_ragged r, const void *d_in, void *d_out, int ft_mode, 
     Guard guard(r->device);
     hipStream_t st = (hipStream_t)hip_stream;
     int rc;
+    if (r->persistent) {
+        if (ft_mode < TFFT_FT_OFF || ft_mode > TFFT_FT_CORRECT) return TFFT_E_INVALID;
+        if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 15)) return TFFT_E_INVALID;
+        const size_t bytes = (size_t)r->extent * (r->dtype == TFFT_C128 ? 16 : 8);
+        const uintptr_t a = (uintptr_t)d_in, b = (uintptr_t)d_out;
+        if ((a < b ? b - a : a - b) < bytes) return TFFT_E_INVALID;  // in place or overlapping
+        if ((rc = persist_tasks(r, d_in, d_out, ft_mode, inverse)) != TFFT_OK) return rc;
+        if (!use_graph) {
+            rc = persist_launch_all(r, ft_mode, st);
+        } else {
+            if (!(r->gexec && r->g_in == d_in && r->g_out == d_out && r->g_mode == ft_mode && r->g_inv == inverse &&
+                  r->g_stream == st)) {
+                drop_graph(r);
+                if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return TFFT_E_HIP;
+                rc = persist_launch_all(r, ft_mode, st);
+                hipGraph_t g = nullptr;
+                const hipError_t e = hipStreamEndCapture(st, &g);
+                if (rc != TFFT_OK || e != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc != TFFT_OK ? rc : TFFT_E_HIP;
+                }
+                r->graph = g;
+                if (hipGraphInstantiate(&r->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+                    drop_graph(r);
+                    return TFFT_E_HIP;
+                }
+                r->g_in = d_in;
+                r->g_out = d_out;
+                r->g_mode = ft_mode;
+                r->g_inv = inverse;
+                r->g_stream = st;
+            }
+            rc = hipGraphLaunch(r->gexec, st) == hipSuccess ? TFFT_OK : TFFT_E_HIP;
+        }
+        if (rc == TFFT_OK) {
+            r->executed = 1;
+            r->last_mode = ft_mode;
+            r->last_stream = st;
+        }
+        return rc;
+    }
     if (!use_graph) {
         rc = ragged_launch(r, d_in, d_out, ft_mode, inverse, st);
     } else {
@@ -1105,7 +1458,39 @@ int tfft_ragged_get_report(tfft_ragged r, tfft_counts *counts, tfft_record *recs
     std::memset(&total, 0, sizeof(total));
     int status = TFFT_OK;
     std::vector<tfft_record> all;
+    if (r->persistent) {
+        // one report for every class: records carry their task (class, pass)
+        DevReport h;
+        int32_t err = 0;
+        if (hipMemcpy(&h, r->d_rep, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(&err, r->d_err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess)
+            return TFFT_E_HIP;
+        if (err) return TFFT_E_HIP;  // a dependency wait gave up: the outputs are not to be trusted
+        const int64_t nrec = std::min<int64_t>((int64_t)h.n_flag, r->rec_cap);
+        std::vector<DevRecord> dr((size_t)nrec);
+        if (nrec > 0 &&
+            hipMemcpy(dr.data(), r->d_recs, sizeof(DevRecord) * (size_t)nrec, hipMemcpyDeviceToHost) != hipSuccess)
+            return TFFT_E_HIP;
+        if (r->last_mode != TFFT_FT_OFF)
+            for (auto &C : r->classes)
+                for (int i = 0; i < C.plan->passes; ++i) total.groups_checked += C.plan->pass[i].n_groups;
+        total.detected = (int64_t)h.n_flag;
+        total.corrected = (int64_t)h.corrected;
+        total.uncorrectable = (int64_t)h.uncorrectable;
+        total.benign = (int64_t)h.benign;
+        total.n_records = nrec;
+        total.dropped = (int64_t)h.n_flag - nrec;
+        for (const DevRecord &d : dr) {
+            if (d.task < 0 || d.task >= (int)r->task_class.size()) continue;
+            const auto &C = r->classes[(size_t)r->task_class[(size_t)d.task]];
+            tfft_record x = host_record(C.plan, d);
+            x.signal = C.members[(size_t)x.signal];
+            all.push_back(x);
+        }
+        if (h.uncorrectable > 0 || (r->last_mode == TFFT_FT_CORRECT && total.dropped > 0)) status = TFFT_UNCORRECTABLE;
+    }
     for (auto &C : r->classes) {
+        if (r->persistent) break;
         tfft_counts c;
         int rc = tfft_get_report(C.plan, &c, nullptr, 0);
         if (rc < 0) return rc;
@@ -1147,6 +1532,12 @@ int tfft_ragged_set_faults(tfft_ragged r, const tfft_fault *specs, int64_t n) {
         per[c].push_back(f);
     }
     drop_graph(r);
+    r->tasks_valid = 0;  // the tasks point at the fault tables
+    if (r->persistent && r->executed) {
+        // the fault tables are replaced: wait for the last execution that reads them
+        Guard guard(r->device);
+        if (hipStreamSynchronize(r->last_stream) != hipSuccess) return TFFT_E_HIP;
+    }
     for (size_t c = 0; c < r->classes.size(); ++c) {
         const int rc = tfft_set_faults(r->classes[c].plan, per[c].data(), (int64_t)per[c].size());
         if (rc != TFFT_OK) return rc;
@@ -1159,6 +1550,7 @@ int tfft_ragged_tune(tfft_ragged r, const void *d_in, void *d_out, void *hip_str
     if (!r || !d_in || !d_out || reps < 1) return TFFT_E_INVALID;
     Guard guard(r->device);
     hipStream_t st = (hipStream_t)hip_stream;
+    if (r->persistent) return persist_tune(r, d_in, d_out, st, reps);
     drop_graph(r);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TFFT_E_HIP;
