@@ -327,7 +327,16 @@ typedef struct tfft_ragged_s *tfft_ragged;
  * dtype as for tfft_plan_create; opt as for tfft_plan_create_with (applied
  * to every class), may be NULL.  E_INVALID: count < 1, a length that is not a
  * power of two in 2..2^24, a negative offset, overlapping signals, a bad
- * dtype or option; E_NOMEM / E_HIP as for plans.  *out is NULL on failure. */
+ * dtype or option; E_NOMEM / E_HIP as for plans.  *out is NULL on failure.
+ *
+ * With TFFT_PERSISTENT in opt->flags (lengths 64..2^24, else E_UNSUPPORTED)
+ * every pass of every class runs in one persistent kernel launch: its
+ * workgroups take work items (a range of at most 64 checksum groups of one
+ * pass of one class) from a device queue, run them, correct the groups they
+ * flagged (CORRECT mode) and release them; an item of pass p > 0 starts once
+ * every item of pass p - 1 covering the same block of 64 signals of its
+ * class is released.  One report serves all classes.  In place is not
+ * supported in this mode (E_INVALID). */
 int tfft_ragged_create(tfft_ragged *out, int64_t count, const int64_t *lengths, const int64_t *offsets, int dtype,
                        const tfft_options *opt);
 /* Free the plans, graphs and streams of r (NULL-safe). */
@@ -352,12 +361,16 @@ int tfft_ragged_get_report(tfft_ragged r, tfft_counts *counts, tfft_record *recs
 int tfft_ragged_set_faults(tfft_ragged r, const tfft_fault *specs, int64_t n);
 
 /* Autotuner (the semi-empirical choice of per-size parameters, TurboFFT
- * Sec. IV-B.3 and Table I, made by measurement): for each length class, time
- * the candidate plans (pass count, checksum group size, workgroups per
- * launch) on the given buffers with fault tolerance CORRECT, `reps`
- * executions each after one warm-up, and keep the fastest.  Overwrites
- * d_out.  Synchronous on hip_stream; drops captured graphs and injected
- * faults (the classes get new plans). */
+ * Sec. IV-B.3 and Table I, made by measurement), timing candidates on the
+ * given buffers with fault tolerance CORRECT, `reps` executions each after
+ * one warm-up.  Per-class plans: for each length class, the candidate plans
+ * (pass count, checksum group size, workgroups per launch), fastest kept.
+ * Persistent plans: coordinate descent over the classes, largest first, on
+ * the time of the whole persistent launch: per class the pass count, the
+ * split of the stages over the passes and the checksum group size (classes
+ * up to 4096 points keep one pass), then the tiles per work item.
+ * Overwrites d_out.  Synchronous on hip_stream; drops captured graphs; the
+ * new class plans get the injected faults of the old ones. */
 int tfft_ragged_tune(tfft_ragged r, const void *d_in, void *d_out, void *hip_stream, int reps);
 
 /* Classes of the ragged plan: their count in *classes and, for the first

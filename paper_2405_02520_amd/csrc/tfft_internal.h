@@ -353,8 +353,8 @@ enum { FT_NONE = 0, FT_BLOCK = 1, FT_SIGNAL = 2, FT_THREAD = 3 };
 // ------------------------------------------------ persistent ragged queue
 // A task is one pass of one length class of a ragged batch; an item is a
 // range of the task's checksum groups; a chunk is a block of the class's
-// signals (a multiple of 64, so that no group straddles two chunks) whose
-// items of pass p must all be released before its items of pass p + 1 start.
+// signals (a whole number of every pass's checksum groups) whose items of
+// pass p must all be released before its items of pass p + 1 start.
 struct PItem {
     int32_t task;
     int32_t chunk;
@@ -366,6 +366,8 @@ struct PTask {
     int32_t dep;        // task of the previous pass of the same class, -1 for none
     int32_t done_base;  // index of this task's chunk 0 in the done / need arrays
     int32_t fix;        // correct flagged groups before releasing the item
+    int32_t publish;    // a later pass reads this task's output: release the items
+    int32_t pad_;
 };
 struct PQueue {
     const PItem *items;

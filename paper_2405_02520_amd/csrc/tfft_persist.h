@@ -94,6 +94,7 @@ __global__ void __launch_bounds__(kPThreads) persist_kernel(PQueue q, const PIte
         const int dep = __builtin_amdgcn_readfirstlane(tk.dep);
         const int done_at = __builtin_amdgcn_readfirstlane(tk.done_base + item.chunk);
         const int fix = __builtin_amdgcn_readfirstlane(tk.fix);
+        const int publish = __builtin_amdgcn_readfirstlane(tk.publish);
         const PassArgs &a = tk.a;
         if (wave == 0) {
             if (dep >= 0) {
@@ -140,10 +141,12 @@ __global__ void __launch_bounds__(kPThreads) persist_kernel(PQueue q, const PIte
                 }
             }
         }
-        // release: every wavefront's stores visible at agent scope, then the count
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // release (when a later pass reads this output): every wavefront's
+        // stores visible at agent scope, then the count
+        if (publish) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (wave == 0) __hip_atomic_fetch_add(q.done + done_at, (int32_t)one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (wave == 0 && publish)
+            __hip_atomic_fetch_add(q.done + done_at, (int32_t)one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -943,7 +943,7 @@ struct tfft_ragged_s {
     // persistent execution (TFFT_PERSISTENT): one kernel drains a queue of
     // work items covering every pass of every class
     int persistent = 0;
-    int64_t item_bytes = 0;               // target bytes moved per work item (0: default)
+    int64_t item_tiles = 0;               // target tiles per work item (0: default)
     std::vector<int> task_class, task_pass;
     std::vector<PItem> h_items;
     int n_done = 0;                       // release counters: one per (task, chunk)
@@ -1038,8 +1038,24 @@ int ragged_launch_branches(tfft_ragged_s *r, const void *d_in, void *d_out, int 
     return rc;
 }
 
-constexpr int64_t kPChunk = 64;                 // signals per dependency chunk
-constexpr int64_t kPItemBytes = int64_t(4) << 20;  // default bytes moved per work item
+constexpr int64_t kPItemTiles = 32;  // default tiles per work item
+
+// Signals per dependency chunk of a class: a multiple of the signals every
+// pass's checksum group spans (so that no group straddles two chunks), at
+// most 64, and otherwise small enough for about 8 chunks per class (so that
+// a later pass starts on the first chunks while the last ones are still in
+// the previous pass).
+int64_t class_chunk(const tfft_plan_s *p) {
+    int64_t span = 1;
+    for (int i = 0; i < p->passes; ++i) {
+        const PassPlan &P = p->pass[i];
+        const int64_t s = P.kind == KIND_ROWS ? P.G : (P.kind == KIND_STRIDED ? (P.rb + P.O - 1) / P.O : P.rb);
+        span = std::max(span, s);
+    }
+    int64_t q = 64;
+    while (q > span && q * 8 > p->batch) q /= 2;
+    return std::max(q, span);
+}
 
 void persist_free(tfft_ragged_s *r) {
     (void)hipFree(r->d_items);
@@ -1060,9 +1076,9 @@ void persist_free(tfft_ragged_s *r) {
 }
 
 // The work queue of a persistent ragged plan from its class plans: tasks
-// (class, pass), chunks of 64 signals per class, items of up to kPSlotCap
-// groups (about item_bytes moved each), and the items per (task, chunk) that
-// a later pass waits for.  Queue order: every multi-pass class's pass 0, then
+// (class, pass), chunks of signals per class (class_chunk), items of up to
+// kPSlotCap groups (about a target number of tiles each), and the items per
+// (task, chunk) that a later pass waits for.  Queue order: every multi-pass class's pass 0, then
 // pass 1, then pass 2 (larger classes first within a level), then the
 // one-pass classes, whose items need nothing and fill the end.
 int persist_build(tfft_ragged_s *r) {
@@ -1083,21 +1099,26 @@ int persist_build(tfft_ragged_s *r) {
     int nd = 0;
     for (int t = 0; t < ntask; ++t) {
         done_base[t] = nd;
-        nd += (int)((r->classes[(size_t)r->task_class[t]].plan->batch + kPChunk - 1) / kPChunk);
+        const tfft_plan_s *pc = r->classes[(size_t)r->task_class[t]].plan;
+        const int64_t q = class_chunk(pc);
+        nd += (int)((pc->batch + q - 1) / q);
     }
     r->n_done = nd;
     std::vector<int32_t> need((size_t)std::max(1, nd), 0);
-    const int64_t target = r->item_bytes > 0 ? r->item_bytes : kPItemBytes;
+    // tiles per item: as tuned, else 32 (an item's start, with its first
+    // load not overlapped, then costs a few percent of its work); items keep
+    // whole groups, at most kPSlotCap of them
+    const int64_t target = r->item_tiles > 0 ? r->item_tiles : kPItemTiles;
     // items per task, in chunk order
     std::vector<std::vector<PItem>> per(ntask);
     for (int t = 0; t < ntask; ++t) {
         const tfft_plan_s *p = r->classes[(size_t)r->task_class[t]].plan;
         const PassPlan &P = p->pass[r->task_pass[t]];
-        const size_t esz = p->dtype == TFFT_C128 ? 16 : 8;
-        const int64_t gbytes = 2 * (int64_t)P.G * P.M * (int64_t)esz;
-        const int64_t K = std::max<int64_t>(1, std::min<int64_t>(kPSlotCap, target / std::max<int64_t>(1, gbytes)));
-        for (int64_t q = 0; q * kPChunk < p->batch; ++q) {
-            const ChunkGeom cg = chunk_geom(p, P, q * kPChunk, std::min(kPChunk, p->batch - q * kPChunk));
+        const int64_t rounds = std::max(1, P.G / std::max(1, P.C));  // tiles per group
+        const int64_t K = std::max<int64_t>(1, std::min<int64_t>(kPSlotCap, target / rounds));
+        const int64_t Q = class_chunk(p);
+        for (int64_t q = 0; q * Q < p->batch; ++q) {
+            const ChunkGeom cg = chunk_geom(p, P, q * Q, std::min(Q, p->batch - q * Q));
             for (int64_t g = cg.g_base; g < cg.g_base + cg.n_groups; g += K) {
                 PItem it;
                 it.task = t;
@@ -1159,7 +1180,8 @@ int persist_tasks(tfft_ragged_s *r, const void *d_in, void *d_out, int mode, int
         k.dep = i > 0 ? t - 1 : -1;
         k.done_base = nd;
         k.fix = mode == TFFT_FT_CORRECT;
-        nd += (int)((p->batch + kPChunk - 1) / kPChunk);
+        k.publish = i + 1 < p->passes;
+        nd += (int)((p->batch + class_chunk(p) - 1) / class_chunk(p));
     }
     if (hipMemcpy(r->d_tasks, tasks.data(), sizeof(PTask) * (size_t)ntask, hipMemcpyHostToDevice) != hipSuccess)
         return TFFT_E_HIP;
@@ -1196,7 +1218,7 @@ int persist_launch_all(tfft_ragged_s *r, int mode, hipStream_t st) {
 // classes (largest first) on the time of the whole persistent execution
 // (FT CORRECT on the caller's buffers): per class the pass count, the split
 // of the stages over the passes and the checksum group size (one-pass classes
-// keep one pass), then the bytes per work item.
+// keep one pass), then the tiles per work item.
 int persist_tune(tfft_ragged_s *r, const void *d_in, void *d_out, hipStream_t st, int reps) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TFFT_E_HIP;
@@ -1256,18 +1278,18 @@ int persist_tune(tfft_ragged_s *r, const void *d_in, void *d_out, hipStream_t st
         status = build_class(r, ci, best_o);
         if (status == TFFT_OK) status = persist_build(r);
     }
-    // bytes moved per work item
-    int64_t best_ib = r->item_bytes;
-    for (int64_t ib : {int64_t(1) << 20, int64_t(2) << 20, int64_t(4) << 20, int64_t(8) << 20}) {
+    // tiles per work item
+    int64_t best_ib = r->item_tiles;
+    for (int64_t ib : {int64_t(8), int64_t(16), int64_t(32), int64_t(64), int64_t(128)}) {
         if (status != TFFT_OK) break;
-        r->item_bytes = ib;
+        r->item_tiles = ib;
         float ms = 0.f;
         if (persist_build(r) == TFFT_OK && time_all(&ms) == TFFT_OK && ms < best) {
             best = ms;
             best_ib = ib;
         }
     }
-    r->item_bytes = best_ib;
+    r->item_tiles = best_ib;
     if (status == TFFT_OK) status = persist_build(r);
     // the new class plans get the faults installed on the old ones
     for (size_t ci = 0; ci < r->classes.size() && status == TFFT_OK; ++ci)
