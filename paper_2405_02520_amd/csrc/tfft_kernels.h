@@ -366,17 +366,23 @@ __device__ __forceinline__ double wave_sum(double v, int width) {
 }
 
 // DPP moves of a 64-bit value (two 32-bit halves); lanes outside row_mask
-// read 0.
+// read 0.  With every row enabled each lane has a valid source, so the move
+// needs no zeroed destination first (one instruction per half, not two).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_b32(int v) {
+    if constexpr (ROWMASK == 0xF) return __builtin_amdgcn_mov_dpp(v, CTRL, ROWMASK, 0xF, false);
+    else return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWMASK, 0xF, false);
+}
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ double dpp64(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWMASK, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+    const int lo = dpp_b32<CTRL, ROWMASK>((int)(b & 0xffffffffll));
+    const int hi = dpp_b32<CTRL, ROWMASK>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ float dpp32(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+    return __int_as_float(dpp_b32<CTRL, ROWMASK>(__float_as_int(v)));
 }
 
 // Sum over a full 64-lane wavefront with DPP lane moves (no LDS traffic):
@@ -962,9 +968,15 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
                     cx<double> cm;
                     if constexpr (CREG) cm = cc[m];
                     else cm = cl[m];
-                    lr += cm.re * xr - cm.im * xi;
-                    li += cm.re * xi + cm.im * xr;
-                    Ssum += xr * xr + xi * xi;  // exact products of binary32 values
+                    // chained fused multiply-adds into the running sums (two
+                    // operations per product pair, not a product, a fused
+                    // product and an add)
+                    lr = __builtin_fma(cm.re, xr, lr);
+                    lr = __builtin_fma(-cm.im, xi, lr);
+                    li = __builtin_fma(cm.re, xi, li);
+                    li = __builtin_fma(cm.im, xr, li);
+                    Ssum = __builtin_fma(xr, xr, Ssum);
+                    Ssum = __builtin_fma(xi, xi, Ssum);
                 }
                 D1r -= lr;
                 D1i -= li;
@@ -1069,8 +1081,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
                             const int cls = ((T % 3) * m) % 3;
                             const double vr = double(v.re), vi = double(v.im);
                             const double pr = P.re, pi = psg * P.im;
-                            Ar[cls] += vr * pr + vi * pi;
-                            Ai[cls] += vi * pr - vr * pi;
+                            Ar[cls] = __builtin_fma(vr, pr, Ar[cls]);
+                            Ar[cls] = __builtin_fma(vi, pi, Ar[cls]);
+                            Ai[cls] = __builtin_fma(vi, pr, Ai[cls]);
+                            Ai[cls] = __builtin_fma(-vr, pi, Ai[cls]);
                         }
                         if (m + 1 < E) P = cmul(P, twB);
                     }
