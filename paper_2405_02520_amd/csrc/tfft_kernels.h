@@ -273,7 +273,13 @@ struct FaultHit {
 __device__ __forceinline__ FaultHit find_fault(const DevFault *F, int fh, int stage, int b, int j) {
     FaultHit h{-1, 0.0, 0.0, 0ull, 0ull};
     for (int f = fh; f >= 0; f = F[f].next) {
-        const DevFault x = F[f];
+        DevFault x = F[f];
+        // every field in registers before any is tested: a load left in
+        // flight on a path that never reads it would make the code after
+        // the fault hook wait for the whole vector-memory queue (the LDS-DMA
+        // prefetch in flight included) before reusing its register
+        asm volatile("" : "+v"(x.member), "+v"(x.stage), "+v"(x.j), "+v"(x.m), "+v"(x.mode), "+v"(x.bit),
+                     "+v"(x.dre), "+v"(x.dim));
         if (x.stage == stage && x.member == b && x.j == j) {
             if (h.m < 0 || h.m == x.m) {
                 h.m = x.m;
@@ -574,15 +580,31 @@ struct PassCfg {
 template <typename R, int M, int KIND, int FT, int NTHR = 0>
 struct PassShared {
     using Cf = PassCfg<R, M, KIND, FT, NTHR>;
-    // 16-byte aligned: the LDS DMA writes 16 bytes per lane into nbuf
     alignas(16) cx<R> lds[Cf::C * M];
-    alignas(16) cx<R> nbuf[Cf::LDSPF ? Cf::C * M : 1];
     double red[Cf::WAVES][5];
     double redg[Cf::RED_DEFER ? 2 : 1][Cf::RED_DEFER ? Cf::WAVES : 1][5];
     cx<R> twl[Cf::TWLDS ? M / 8 + 1 : 1];
     double redm[Cf::SIGM && KIND == KIND_STRIDED ? Cf::WAVES : 1][Cf::SIGM && KIND == KIND_STRIDED ? Cf::C : 1][3];
     DevFault f0;
 };
+
+// The LDS-DMA prefetch buffer (16-byte aligned: the DMA writes 16 bytes per
+// lane) is an LDS variable of its own, not a member of PassShared: accesses
+// to distinct LDS variables carry distinct alias scopes, so the compiler
+// knows that the stage exchanges through `lds` do not touch the buffer the
+// DMA in flight is writing, and does not wait for the DMA before them.
+template <typename R, int M, int KIND, int FT, int NTHR = 0>
+constexpr int pass_nbuf_elems() {
+    using Cf = PassCfg<R, M, KIND, FT, NTHR>;
+    return Cf::LDSPF ? Cf::C * M : 1;
+}
+
+// Workgroup barrier for LDS traffic only: the wavefront's LDS operations
+// complete, then s_barrier; the memory clobber keeps the compiler from moving
+// memory operations across it.  __syncthreads also waits for the
+// wavefront's LDS-DMA loads in flight (its release fence covers LDS written
+// by DMA), which would end the next tile's prefetch at the first exchange.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Optional per-call hooks of pass_body: `slots` collects the record slots the
 // call appends (the persistent kernel corrects them before it releases the
@@ -596,8 +618,8 @@ struct PassHooks {
 // The groups g_first, g_first + g_step, ... (< g_end) of one pass, processed
 // by one workgroup of PassCfg::NT threads with the LDS of `sh`.
 template <typename R, int M, int KIND, int FT, int NTHR>
-__device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KIND, FT, NTHR> &sh, int64_t g_first,
-                                          int64_t g_end, int64_t g_step, const PassHooks &hk) {
+__device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KIND, FT, NTHR> &sh, cx<R> *nbuf,
+                                          int64_t g_first, int64_t g_end, int64_t g_step, const PassHooks &hk) {
     using Cf = PassCfg<R, M, KIND, FT, NTHR>;
     constexpr int FP64 = Cf::FP64;
     constexpr bool BLK = Cf::BLK, SIG = Cf::SIG, THR = Cf::THR;
@@ -620,6 +642,11 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
     auto &lds = sh.lds;
     auto &red = sh.red;
     auto &redg = sh.redg;
+    // the barriers of the pass: LDS-only where a DMA prefetch may be in flight
+    auto tile_sync = [] {
+        if constexpr (Cf::LDSPF) lds_barrier();
+        else __syncthreads();
+    };
 
     int tid = threadIdx.x;
     // persistent kernel: an opaque copy per call, so that what derives from
@@ -654,7 +681,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
     auto &twl = sh.twl;
     if constexpr (TWLDS) {
         for (int t = tid; t <= M / 8; t += NT) twl[t] = ldg(stw + t);
-        __syncthreads();
+        tile_sync();
     }
     auto tw_oct = [&](int t) -> cx<R> {
         constexpr int M4 = M / 4, M8 = M / 8;
@@ -736,14 +763,20 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
     // m NT + tid, and a thread reads back only what its own lane wrote.
     constexpr bool LDSPF = Cf::LDSPF;
     constexpr bool PREFETCH = Cf::PREFETCH;
-    auto &nbuf = sh.nbuf;
     auto nslot = [&](int m) -> int { return tid + NT * m; };
     auto dma_tile = [&](int64_t gg, int rr) {
         if constexpr (LDSPF) {
             static_assert(NT % 64 == 0 && sizeof(cx<R>) == 16, "LDS prefetch: 16-byte elements, full wavefronts");
             const MemberLoc Ln = mloc(gg, rr);
+            // A member's offset may come from a table load (ragged plans).
+            // Resolve it here, on every path: a load still pending where the
+            // DMA is skipped would make the compiler wait for the whole
+            // vector-memory queue, the DMA just issued included, at the
+            // transform's first use of the register.
+            int64_t in_off = Ln.in_off;
+            asm volatile("" : "+v"(in_off));
             if (gg < n_iter && Ln.valid) {
-                const cx<R> *src = in + Ln.in_off;
+                const cx<R> *src = in + in_off;
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int base = nslot(m) - (tid & 63);  // wavefront-uniform
@@ -793,7 +826,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
 #pragma unroll
                     for (int q = 0; q < 3; ++q) redm[tid >> 6][tid & 63][q] = v[q];
                 }
-                __syncthreads();
+                tile_sync();
                 if (tid < C) {
                     v[0] = v[1] = v[2] = 0.0;
                     for (int w = 0; w < WAVES; ++w)
@@ -814,7 +847,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
 #pragma unroll
                     for (int q = 0; q < 3; ++q) red[tid >> 6][q] = v[q];
                 }
-                __syncthreads();
+                tile_sync();
                 if (j == 0) {
                     v[0] = v[1] = v[2] = 0.0;
                     for (int w = c * (T / 64); w < (c + 1) * (T / 64); ++w)
@@ -845,7 +878,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
                 }
             }
         }
-        if constexpr (NT > 64) __syncthreads();
+        if constexpr (NT > 64) tile_sync();
     };
     // a group's decision from its five sums (one thread)
     auto decide = [&](const double *t, int64_t g) {
@@ -900,9 +933,9 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
         bool fmulti = true;
         if constexpr (!SIGR) {
             if (fh >= 0) {
-                __syncthreads();
+                tile_sync();
                 if (tid == 0) f0 = a.faults[fh];
-                __syncthreads();
+                tile_sync();
                 fmulti = f0.next >= 0;
             }
         }
@@ -1005,7 +1038,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
                 if constexpr (s > 0) {
 #pragma unroll
                     for (int m = 0; m < E; ++m) d[m] = lds[lidx(c, j + T * m)];
-                    __syncthreads();
+                    tile_sync();
                     static_for<0, NB>([&](auto p) {
                         static_for<1, RAD>([&](auto q) {
                             cx<R> w;
@@ -1044,7 +1077,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
                         const int base = (i / NS) * NS * RAD + (i % NS);
                         static_for<0, RAD>([&](auto q) { lds[lidx(c, base + q * NS)] = d[p + q * NB]; });
                     });
-                    __syncthreads();
+                    tile_sync();
                 }
             });
 
@@ -1135,7 +1168,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
                 // the C adjacent output rows of the tile
 #pragma unroll
                 for (int m = 0; m < E; ++m) lds[lidx(c, j + T * m)] = d[m];
-                __syncthreads();
+                tile_sync();
                 const int c2 = tid % C, j2 = tid / C;
                 cx<R> *base = dst - c + c2;  // rows of one tile share the batch entry
                 if constexpr (DEFER) {
@@ -1149,7 +1182,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
                     for (int m = 0; m < E; ++m)
                         st_stream<R, NT_ST>(base + (uint32_t)(j2 + T * m) * ostr, lds[lidx(c2, j2 + T * m)]);
                 }
-                __syncthreads();
+                tile_sync();
             } else if constexpr (DEFER) {
 #pragma unroll
                 for (int m = 0; m < E; ++m) ps[m] = d[m];
@@ -1176,13 +1209,13 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
                 // up by one wavefront: each thread stores five values instead
                 // of running five 64-bit DPP reductions
                 double *part = reinterpret_cast<double *>(lds);
-                __syncthreads();
+                tile_sync();
                 part[tid] = D1r;
                 part[NT + tid] = D1i;
                 part[2 * NT + tid] = D2r;
                 part[3 * NT + tid] = D2i;
                 part[4 * NT + tid] = Ssum;
-                __syncthreads();
+                tile_sync();
                 if (tid < 64) {
                     double v[5];
 #pragma unroll
@@ -1193,7 +1226,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
                     }
                     if (tid == 63) decide(v, g);
                 }
-                __syncthreads();
+                tile_sync();
             } else {
                 double v[5] = {D1r, D1i, D2r, D2i, 0.0};
                 if constexpr (NT % 64 == 0) {
@@ -1229,21 +1262,21 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
                     g_prev = g;
                     ++it;
                 } else {
-                    __syncthreads();
+                    tile_sync();
                     if (tid == 0) {
                         double t[5] = {0, 0, 0, 0, 0};
                         for (int w = 0; w < WAVES; ++w)
                             for (int k = 0; k < 5; ++k) t[k] += red[w][k];
                         decide(t, g);
                     }
-                    __syncthreads();
+                    tile_sync();
                 }
             }
         }
     }  // groups
     if constexpr (RED_DEFER) {
         // the last group's decision
-        __syncthreads();
+        tile_sync();
         if (tid == 0 && g_prev >= 0) {
             double t[5] = {0, 0, 0, 0, 0};
             for (int w = 0; w < WAVES; ++w)
@@ -1259,13 +1292,14 @@ __global__ void __launch_bounds__(cfg_threads(sizeof(R) == 8, M, KIND)) TFFT_PAS
 pass_kernel(PassArgs a) {
     using Cf = PassCfg<R, M, KIND, FT>;
     __shared__ PassShared<R, M, KIND, FT> sh;
+    __shared__ __align__(16) cx<R> nbuf[pass_nbuf_elems<R, M, KIND, FT>()];
     // XCD-contiguous group ranges: consecutive workgroups run on different
     // XCDs, so workgroup b walks the groups of slot (b mod 8, b / 8)
     const int nwg = gridDim.x;
     int64_t wl = blockIdx.x;
     if (nwg % 8 == 0) wl = (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
     const int64_t n_iter = Cf::SIGR ? (a.n_groups + Cf::C - 1) / Cf::C : a.n_groups;
-    pass_body<R, M, KIND, FT, 0>(a, sh, wl, n_iter, nwg, PassHooks{nullptr, nullptr, 0});
+    pass_body<R, M, KIND, FT, 0>(a, sh, nbuf, wl, n_iter, nwg, PassHooks{nullptr, nullptr, 0});
 }
 
 // ------------------------------------------------------- correction kernel

@@ -42,14 +42,31 @@ constexpr size_t persist_pool_bytes() {
 #undef TFFT_PV_MAX
     return (m + 15) / 16 * 16;
 }
+// the LDS-DMA prefetch buffer, an LDS variable of its own (as in pass_kernel)
+template <typename R, int FT>
+constexpr size_t persist_nbuf_bytes() {
+    size_t m = 0;
+#define TFFT_PV_NB(K, MM)                                                         \
+    m = sizeof(cx<R>) * pass_nbuf_elems<R, MM, K, FT, kPThreads>() > m            \
+            ? sizeof(cx<R>) * pass_nbuf_elems<R, MM, K, FT, kPThreads>()          \
+            : m;
+    TFFT_PVARIANTS(TFFT_PV_NB)
+#undef TFFT_PV_NB
+    return (m + 15) / 16 * 16;
+}
 
-// Wait until *p >= target (acquire, agent scope); false after `limit` polls.
+// Wait until *p >= target, then acquire at agent scope; false after `limit`
+// polls.  The polls are relaxed atomic loads and the acquire is one fence
+// after the last: an acquiring load per poll would invalidate the caches of
+// the workgroup's chiplet at every poll, under the feet of the workgroups
+// still streaming through them.
 __device__ __forceinline__ bool wait_count(const int32_t *p, int32_t target, int64_t limit) {
     int64_t n = 0;
-    while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         if (++n > limit) return false;
         __builtin_amdgcn_s_sleep(4);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
@@ -60,8 +77,10 @@ template <typename R, int FT>
 __global__ void __launch_bounds__(kPThreads) persist_kernel(PQueue q, const PItem *__restrict__ items,
                                                             const PTask *__restrict__ tasks) {
     constexpr size_t POOL = persist_pool_bytes<R, FT>();
-    static_assert(POOL <= 150 * 1024, "persistent kernel LDS");
+    constexpr size_t NPOOL = persist_nbuf_bytes<R, FT>();
+    static_assert(POOL + NPOOL <= 150 * 1024, "persistent kernel LDS");
     __shared__ __align__(16) unsigned char pool[POOL];
+    __shared__ __align__(16) unsigned char npool[NPOOL];
     __shared__ int64_t slots[kPSlotCap];
     __shared__ int n_slots;
     __shared__ int64_t cur;
@@ -111,7 +130,7 @@ __global__ void __launch_bounds__(kPThreads) persist_kernel(PQueue q, const PIte
 #define TFFT_PV_RUN(K, MM)                                                                                     \
     case pvariant_id(K, MM):                                                                                   \
         pass_body<R, MM, K, FT, kPThreads>(a, *reinterpret_cast<PassShared<R, MM, K, FT, kPThreads> *>(pool), \
-                                           item.g0, item.g1, 1, hk);                                           \
+                                           reinterpret_cast<cx<R> *>(npool), item.g0, item.g1, 1, hk);         \
         break;
             TFFT_PVARIANTS(TFFT_PV_RUN)
 #undef TFFT_PV_RUN
