@@ -606,6 +606,18 @@ constexpr int pass_nbuf_elems() {
 // by DMA), which would end the next tile's prefetch at the first exchange.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Wait for every vector-memory operation of the wavefront (vmcnt(0)) with
+// the compiler's own wait instruction, between two compiler barriers for
+// memory operations.  Written as inline asm the wait is opaque to the
+// compiler's wait-count insertion, which then still counts the older loads
+// as outstanding and waits for them again later, after newer stores (and so
+// for those stores too).
+__device__ __forceinline__ void vm_wait_all() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt 0; expcnt, lgkmcnt not waited
+    asm volatile("" ::: "memory");
+}
+
 // Optional per-call hooks of pass_body: `slots` collects the record slots the
 // call appends (the persistent kernel corrects them before it releases the
 // item), at most `slot_cap` of them, counted in *n_slots.
@@ -1023,7 +1035,11 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
             if constexpr (LDSPF && KIND == KIND_STRIDED)
                 asm volatile("" : "+v"(twA.re), "+v"(twA.im), "+v"(twB.re), "+v"(twB.im));
             if constexpr (LDSPF) {
-                asm volatile("" ::: "memory");
+                // Nothing older than the next tile's DMA outstanding in the
+                // compiler's count (the previous tile's deferred stores have
+                // drained by now): an older store still counted would make
+                // the first exchange after the DMA wait for the whole queue.
+                vm_wait_all();
                 if (r + 1 < rounds) dma_tile(g, r + 1);
                 else dma_tile(g + g_step, 0);
             }
