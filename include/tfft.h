@@ -66,8 +66,11 @@ enum tfft_status {
 /* Plan flags. */
 enum tfft_flags {
     TFFT_INVERSE_UNSCALED = 1u << 0, /* exec_inverse omits the 1/N factor */
-    TFFT_PERSISTENT = 1u << 1        /* ragged plans only: every class's passes run in one
+    TFFT_PERSISTENT = 1u << 1,       /* ragged plans only: every class's passes run in one
                                         persistent kernel launch draining a work queue */
+    TFFT_PERSIST_INTERLEAVE = 1u << 2 /* with TFFT_PERSISTENT: the work items of a block of
+                                        signals take every n-th checksum group instead of a
+                                        range of them (tfft_ragged_tune chooses either) */
 };
 
 /* Record actions. */
@@ -336,7 +339,10 @@ typedef struct tfft_ragged_s *tfft_ragged;
  * flagged (CORRECT mode) and release them; an item of pass p > 0 starts once
  * every item of pass p - 1 covering the same block of 64 signals of its
  * class is released.  One report serves all classes.  In place is not
- * supported in this mode (E_INVALID). */
+ * supported in this mode (E_INVALID).  With TFFT_PERSIST_INTERLEAVE as well,
+ * the items of a block of signals take every n-th of its checksum groups
+ * (n = the number of items) instead of a range, so that the workgroups
+ * running them side by side work on neighbouring strips of the data. */
 int tfft_ragged_create(tfft_ragged *out, int64_t count, const int64_t *lengths, const int64_t *offsets, int dtype,
                        const tfft_options *opt);
 /* Free the plans, graphs and streams of r (NULL-safe). */

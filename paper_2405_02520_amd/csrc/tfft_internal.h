@@ -358,7 +358,8 @@ enum { FT_NONE = 0, FT_BLOCK = 1, FT_SIGNAL = 2, FT_THREAD = 3 };
 struct PItem {
     int32_t task;
     int32_t chunk;
-    int64_t g0, g1;  // groups [g0, g1) of the task's pass
+    int64_t g0, g1;  // groups g0, g0 + step, ... below g1 of the task's pass
+    int64_t step;
 };
 struct PTask {
     PassArgs a;         // the pass: tables, buffers, geometry, report (g_base = 0)

@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(kPThreads) persist_kernel(PQueue q, const PIte
 #define TFFT_PV_RUN(K, MM)                                                                                     \
     case pvariant_id(K, MM):                                                                                   \
         pass_body<R, MM, K, FT, kPThreads>(a, *reinterpret_cast<PassShared<R, MM, K, FT, kPThreads> *>(pool), \
-                                           reinterpret_cast<cx<R> *>(npool), item.g0, item.g1, 1, hk);         \
+                                           reinterpret_cast<cx<R> *>(npool), item.g0, item.g1, item.step, hk); \
         break;
             TFFT_PVARIANTS(TFFT_PV_RUN)
 #undef TFFT_PV_RUN

@@ -533,8 +533,9 @@ int shape_plan(tfft_plan_s *p, int64_t n, int64_t batch, int dtype, const tfft_o
     const int Guser = opt ? opt->group : 0;
     if (Guser < 0 || Guser > 64 || (Guser & (Guser - 1)) != 0) return TFFT_E_INVALID;
     if (opt && (opt->kappa < 0 || !std::isfinite(opt->kappa))) return TFFT_E_INVALID;
-    if (flags & ~(uint32_t)(TFFT_INVERSE_UNSCALED | TFFT_PERSISTENT)) return TFFT_E_INVALID;
+    if (flags & ~(uint32_t)(TFFT_INVERSE_UNSCALED | TFFT_PERSISTENT | TFFT_PERSIST_INTERLEAVE)) return TFFT_E_INVALID;
     if ((flags & TFFT_PERSISTENT) && !ragged) return TFFT_E_INVALID;  // a ragged-batch mode
+    if ((flags & TFFT_PERSIST_INTERLEAVE) && !(flags & TFFT_PERSISTENT)) return TFFT_E_INVALID;
     const int split = opt ? opt->split : 0;
     if (split < 0 || split > 1) return TFFT_E_INVALID;
     const int force_passes = opt ? opt->passes : 0;
@@ -944,6 +945,7 @@ struct tfft_ragged_s {
     // work items covering every pass of every class
     int persistent = 0;
     int64_t item_tiles = 0;               // target tiles per work item (0: default)
+    int item_interleave = 0;              // items of a chunk take every n-th group (1) or a range (0)
     std::vector<int> task_class, task_pass;
     std::vector<PItem> h_items;
     int n_done = 0;                       // release counters: one per (task, chunk)
@@ -1119,12 +1121,23 @@ int persist_build(tfft_ragged_s *r) {
         const int64_t Q = class_chunk(p);
         for (int64_t q = 0; q * Q < p->batch; ++q) {
             const ChunkGeom cg = chunk_geom(p, P, q * Q, std::min(Q, p->batch - q * Q));
-            for (int64_t g = cg.g_base; g < cg.g_base + cg.n_groups; g += K) {
+            const int64_t n_it = (cg.n_groups + K - 1) / K;
+            for (int64_t i = 0; i < n_it; ++i) {
                 PItem it;
                 it.task = t;
                 it.chunk = (int32_t)q;
-                it.g0 = g;
-                it.g1 = std::min(g + K, cg.g_base + cg.n_groups);
+                if (r->item_interleave) {
+                    // item i takes groups i, i + n_it, ...: the workgroups
+                    // running the chunk's items side by side work on
+                    // neighbouring strips at the same time
+                    it.g0 = cg.g_base + i;
+                    it.g1 = cg.g_base + cg.n_groups;
+                    it.step = n_it;
+                } else {
+                    it.g0 = cg.g_base + i * K;
+                    it.g1 = std::min(it.g0 + K, cg.g_base + cg.n_groups);
+                    it.step = 1;
+                }
                 per[t].push_back(it);
                 ++need[(size_t)(done_base[t] + q)];
             }
@@ -1290,6 +1303,18 @@ int persist_tune(tfft_ragged_s *r, const void *d_in, void *d_out, hipStream_t st
         }
     }
     r->item_tiles = best_ib;
+    // contiguous or interleaved group ranges per item
+    int best_il = r->item_interleave;
+    for (int il : {0, 1}) {
+        if (status != TFFT_OK) break;
+        r->item_interleave = il;
+        float ms = 0.f;
+        if (persist_build(r) == TFFT_OK && time_all(&ms) == TFFT_OK && ms < best) {
+            best = ms;
+            best_il = il;
+        }
+    }
+    r->item_interleave = best_il;
     if (status == TFFT_OK) status = persist_build(r);
     // the new class plans get the faults installed on the old ones
     for (size_t ci = 0; ci < r->classes.size() && status == TFFT_OK; ++ci)
@@ -1347,6 +1372,7 @@ int tfft_ragged_create(tfft_ragged *out, int64_t count, const int64_t *lengths, 
         r->classes[c].members.push_back(i);
     }
     r->persistent = (r->opt.flags & TFFT_PERSISTENT) ? 1 : 0;
+    r->item_interleave = (r->opt.flags & TFFT_PERSIST_INTERLEAVE) ? 1 : 0;
     for (size_t c = 0; c < r->classes.size(); ++c) {
         const int rc = build_class(r, c, r->opt);
         if (rc != TFFT_OK) {

@@ -85,12 +85,12 @@ def test_persistent_rejects_short_lengths(tf):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("gaps", [False, True])
-def test_persistent_forward_matches_oracle(tf, dtype, gaps):
+@pytest.mark.parametrize("gaps,interleave", [(False, False), (True, False), (False, True), (True, True)])
+def test_persistent_forward_matches_oracle(tf, dtype, gaps, interleave):
     lengths, offsets, total = layout(inputs.SEED_RAGGED + 10, 300, 6, 16, gaps)
     x = inputs.uniform_flat(inputs.SEED_RAGGED + 10, total, NPDT[dtype])
-    print(f"persistent forward {dtype} gaps={gaps} total={total}", flush=True)
-    rg = tf.Ragged(lengths, offsets, dtype, persistent=True)
+    print(f"persistent forward {dtype} gaps={gaps} interleave={interleave} total={total}", flush=True)
+    rg = tf.Ragged(lengths, offsets, dtype, persistent=True, interleave=interleave)
     xd = to_dev(x)
     out = to_dev(np.full(total, 7 + 7j, NPDT[dtype]))
     rg.forward(xd, out)
@@ -128,13 +128,13 @@ def test_persistent_equals_class_launches(tf, dtype):
     check_signals(x, yi, lengths, offsets, dtype, idx=range(0, 200, 3), inverse=True)
 
 
-@pytest.mark.parametrize("dtype", ["c64", "c128"])
-def test_persistent_faults_are_corrected(tf, dtype):
+@pytest.mark.parametrize("dtype,interleave", [("c64", False), ("c128", False), ("c64", True), ("c128", True)])
+def test_persistent_faults_are_corrected(tf, dtype, interleave):
     lengths, offsets, total = layout(inputs.SEED_RAGGED + 12, 400, 6, 17, True)
     x = inputs.uniform_flat(inputs.SEED_RAGGED + 12, total, NPDT[dtype])
-    rg = tf.Ragged(lengths, offsets, dtype, persistent=True)
+    rg = tf.Ragged(lengths, offsets, dtype, persistent=True, interleave=interleave)
     specs, sigs = fault_specs(rg, lengths, inputs.fault_rng(inputs.SEED_RAGGED + 12), 0.03)
-    print(f"persistent faults {dtype}: {len(specs)}", flush=True)
+    print(f"persistent faults {dtype} interleave={interleave}: {len(specs)}", flush=True)
     rg.set_faults(specs)
     y = rg.forward(to_dev(x)).cpu().numpy()
     counts, recs = rg.report()
