@@ -52,12 +52,17 @@ def parse():
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="turn rocprofv3 --pmc output directories DIR/<label>_<FETCH_SIZE|WRITE_SIZE> (label: copy "
                          "or <dtype>_k<k>) into profiles/pmc_traffic.json")
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "grad", "bitflip", "ragged", "schemes", "calibrate"],
+    ap.add_argument("--workload", default="sweep",
+                    choices=["sweep", "grad", "bitflip", "ragged", "ragged-class", "schemes", "calibrate"],
                     help="sweep: the throughput sweep (default, the headline line); grad: the differentiable "
                          "layer, complex64 [2048, 4096] forward + backward; bitflip: the fault-coverage campaign; "
                          "ragged: 4096 complex64 signals of lengths 2^U{6..20} in one graph launch; schemes: checksum "
                          "overhead of the block, one-sided and thread-level schemes, N = 2^8..2^16; calibrate: noise-scaled "
-                         "checksum residuals of >= 10^6 fault-free groups per precision (the threshold factor kappa)")
+                         "checksum residuals of >= 10^6 fault-free groups per precision (the threshold factor kappa); "
+                         "ragged-class: one length class (--class-log2, --class-count) as per-class launches and as "
+                         "one persistent launch, side by side")
+    ap.add_argument("--class-log2", type=int, default=19, help="ragged-class: log2 of the signal length")
+    ap.add_argument("--class-count", type=int, default=64, help="ragged-class: number of signals")
     ap.add_argument("--ft", default="correct", choices=["off", "detect", "correct"],
                     help="fault-tolerance mode of the timed workload (the headline uses correct)")
     return ap.parse_args()
@@ -495,6 +500,42 @@ def bench_calibrate(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_ragged_class(args):
+    """One length class of a ragged batch (complex64, FT CORRECT, no faults):
+    the per-class launches and the persistent launch (interleaved items) of
+    the same signals, each replayed as a graph --steps times after --warmup
+    replays; prints both times per replay (a comparison of the two forms,
+    and the command its counter profiles are taken with)."""
+    import numpy as np
+    import torch
+
+    import paper_2405_02520_amd as tf
+    import tfft_inputs as inputs
+
+    n = 1 << args.class_log2
+    lengths = np.full(args.class_count, n, np.int64)
+    xd = torch.from_numpy(inputs.uniform_flat(inputs.SEED_RAGGED, int(lengths.sum()), np.complex64)).cuda()
+    out = torch.empty_like(xd)
+    st = torch.cuda.Stream()
+    res = {}
+    for name, pers in (("per_class", False), ("persistent", True)):
+        rg = tf.Ragged(lengths, dtype="c64", persistent=pers, interleave=pers)
+        with torch.cuda.stream(st):
+            for _ in range(max(1, args.warmup)):
+                rg.forward(xd, out, ft_mode=args.ft, use_graph=True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(args.steps):
+                rg.forward(xd, out, ft_mode=args.ft, use_graph=True)
+            e1.record(st)
+        e1.synchronize()
+        res[f"ms_{name}"] = round(e0.elapsed_time(e1) / args.steps, 4)
+        rg.close()
+    print(json.dumps({"workload": "ragged-class", "n": n, "signals": args.class_count, "ft": args.ft,
+                      "steps": args.steps, **res,
+                      "ratio": round(res["ms_persistent"] / res["ms_per_class"], 3)}), flush=True)
+
+
 def main():
     args = parse()
     if args.workload == "calibrate":
@@ -503,6 +544,8 @@ def main():
         return bench_schemes(args)
     if args.workload == "ragged":
         return bench_ragged(args)
+    if args.workload == "ragged-class":
+        return bench_ragged_class(args)
     if args.workload == "grad":
         return bench_grad(args)
     if args.workload == "bitflip":
