@@ -68,9 +68,12 @@ enum tfft_flags {
     TFFT_INVERSE_UNSCALED = 1u << 0, /* exec_inverse omits the 1/N factor */
     TFFT_PERSISTENT = 1u << 1,       /* ragged plans only: every class's passes run in one
                                         persistent kernel launch draining a work queue */
-    TFFT_PERSIST_INTERLEAVE = 1u << 2 /* with TFFT_PERSISTENT: the work items of a block of
-                                        signals take every n-th checksum group instead of a
-                                        range of them (tfft_ragged_tune chooses either) */
+    TFFT_PERSIST_INTERLEAVE = 1u << 2, /* with TFFT_PERSISTENT: the work items of a block of
+                                         signals take every n-th checksum group instead of a
+                                         range of them (tfft_ragged_tune chooses either) */
+    TFFT_PERSIST_ONE_QUEUE = 1u << 3   /* with TFFT_PERSISTENT: one work queue for all
+                                         workgroups instead of one per XCD (tfft_ragged_tune
+                                         chooses either) */
 };
 
 /* Record actions. */
@@ -342,7 +345,10 @@ typedef struct tfft_ragged_s *tfft_ragged;
  * supported in this mode (E_INVALID).  With TFFT_PERSIST_INTERLEAVE as well,
  * the items of a block of signals take every n-th of its checksum groups
  * (n = the number of items) instead of a range, so that the workgroups
- * running them side by side work on neighbouring strips of the data. */
+ * running them side by side work on neighbouring strips of the data.  The
+ * items sit in 8 queues, one per XCD (TFFT_PERSIST_ONE_QUEUE: a single
+ * one), every item of a block of signals in the same queue; a workgroup
+ * serves its own XCD's queue first and the others once it is drained. */
 int tfft_ragged_create(tfft_ragged *out, int64_t count, const int64_t *lengths, const int64_t *offsets, int dtype,
                        const tfft_options *opt);
 /* Free the plans, graphs and streams of r (NULL-safe). */

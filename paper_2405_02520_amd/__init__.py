@@ -36,6 +36,7 @@ SCRATCH_BYTES = 64 << 20  # the library's static device scratch (tfft_exec_noall
 INVERSE_UNSCALED = 1
 PERSISTENT = 2
 PERSIST_INTERLEAVE = 4
+PERSIST_ONE_QUEUE = 8
 ACT_DETECTED, ACT_CORRECTED, ACT_BENIGN, ACT_UNCORRECTABLE = 1, 2, 3, 4
 LOC_NONE, LOC_QUOTIENT, LOC_PER_SIGNAL, LOC_THREAD, LOC_SUBSIGNAL = 0, 1, 2, 3, 4
 SCHEME_BLOCK, SCHEME_SIGNAL, SCHEME_THREAD = 0, 1, 2
@@ -304,11 +305,12 @@ class Ragged:
     replays all launches of all classes as one captured HIP graph."""
 
     def __init__(self, lengths, offsets=None, dtype="c64", group: int = 0, kappa: float = 0.0,
-                 persistent: bool = False, interleave: bool = False):
+                 persistent: bool = False, interleave: bool = False, one_queue: bool = False):
         """persistent: every pass of every class runs in one persistent kernel
         launch that drains a queue of work items (lengths 64..2^24);
         interleave: its items take every n-th checksum group of a block of
-        signals instead of a range (the tuner may change it)."""
+        signals instead of a range; one_queue: a single work queue instead of
+        one per XCD (the tuner may change both)."""
         import numpy as np
         self.lengths = np.asarray(lengths, dtype=np.int64)
         if offsets is None:
@@ -317,7 +319,8 @@ class Ragged:
         self.count = int(len(self.lengths))
         self.extent = int((self.offsets + self.lengths).max()) if self.count else 0
         self.dtype_code = _dtype_code(dtype)
-        flags = (PERSISTENT if persistent else 0) | (PERSIST_INTERLEAVE if interleave else 0)
+        flags = ((PERSISTENT if persistent else 0) | (PERSIST_INTERLEAVE if interleave else 0) |
+                 (PERSIST_ONE_QUEUE if one_queue else 0))
         opt = tfft_options(flags=flags, group=int(group), kappa=float(kappa))
         self.persistent = bool(persistent)
         ln = np.ascontiguousarray(self.lengths)

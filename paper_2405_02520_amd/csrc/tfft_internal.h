@@ -371,15 +371,19 @@ struct PTask {
     int32_t pad_;
 };
 struct PQueue {
-    const PItem *items;
-    int64_t n_items;
+    const PItem *items;        // the queues' items, queue after queue
+    int64_t n_items;           // all queues together
     const PTask *tasks;
-    unsigned long long *head;  // next item to take
+    unsigned long long *head;  // next item to take, per queue
+    const int64_t *q_begin;    // queue k holds items [q_begin[k], q_begin[k + 1])
+    int32_t n_queues;          // 1..kPQueues
+    int32_t pad_;
     int32_t *done;             // items released, per (task, chunk)
     const int32_t *need;       // items, per (task, chunk)
     int32_t *err;              // bit 0: a dependency wait ran out; bit 1: unknown variant
     int64_t spin_limit;        // polls of a dependency wait before it gives up
 };
+constexpr int kPQueues = 8;  // at most one work queue per XCD
 constexpr int pvariant_id(int kind, int M) { return kind * 16 + ilog2c(M); }
 constexpr int kPersistThreads = 512;  // threads of the persistent workgroup
 constexpr int kPSlotCap = 64;         // groups per item (each flags at most one record)

@@ -115,8 +115,8 @@ int persist_occupancy(int fp64, int ft) {
 __global__ void persist_reset_kernel(PQueue q, int n_done, DevReport *rep) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_done) q.done[i] = 0;
+    if (i < kPQueues) q.head[i] = 0;
     if (i == 0) {
-        *q.head = 0;
         *q.err = 0;
         rep->n_flag = 0;
         rep->corrected = 0;

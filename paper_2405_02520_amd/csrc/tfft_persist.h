@@ -8,9 +8,12 @@
 // input: the delayed, batched correction of Section III-B, done before the
 // data move on), and releases the item.  Items of pass p > 0 of a class wait
 // until every item of pass p - 1 covering the same block of signals (a
-// "chunk") is released.  Items are taken in queue order, and an item only
-// waits on items earlier in the queue, which running workgroups hold: the
-// waits end whatever the number of resident workgroups.  Each wait is
+// "chunk") is released.  The items sit in up to 8 queues (one per XCD), all
+// items of a chunk in the same queue; a workgroup takes items from its own
+// queue, then from the others once it is drained.  Each queue's items are
+// taken in order and an item only waits on items earlier in its own queue,
+// which running workgroups hold: the waits end whatever the number of
+// resident workgroups.  Each wait is
 // bounded all the same (an error flag, then the workgroup moves on), so every
 // wavefront reaches the end of the kernel.
 #include "tfft_kernels.h"
@@ -98,15 +101,32 @@ __global__ void __launch_bounds__(kPThreads) persist_kernel(PQueue q, const PIte
         return (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32)) << 32) |
                          (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u));
     };
+    // Queues: workgroup b serves queue b mod n_queues first (consecutive
+    // workgroups run on different XCDs, so each XCD works through the items
+    // of its own queue), then the others in turn once its own is drained.
+    // Every item's dependencies sit earlier in its own queue, and a queue's
+    // items are taken in order, so the waits end as with a single queue.
+    const int home = (int)(blockIdx.x % (unsigned)q.n_queues);
+    int tried = 0;  // queues found drained (wavefront 0)
     for (;;) {
         if (wave == 0) {
-            // one increment per workgroup: lane 0 adds 1, the others 0
-            const unsigned long long got = atomicAdd(q.head, (unsigned long long)one);
-            cur = uniform64((int64_t)got);  // lane 0's value, the same in every lane
+            int64_t got = -1;
+            while (__builtin_amdgcn_readfirstlane(tried) < q.n_queues) {
+                const int k = __builtin_amdgcn_readfirstlane((home + tried) % q.n_queues);
+                // one increment per workgroup: lane 0 adds 1, the others 0
+                const int64_t t = uniform64((int64_t)atomicAdd(q.head + k, (unsigned long long)one));
+                const int64_t b0 = q.q_begin[k], b1 = q.q_begin[k + 1];
+                if (b0 + t < b1) {
+                    got = b0 + t;
+                    break;
+                }
+                ++tried;
+            }
+            cur = got;  // -1: every queue drained
         }
         __syncthreads();
         const int64_t it = uniform64(cur);
-        if (it >= q.n_items) break;
+        if (it < 0) break;
         const PItem item = items[it];
         const PTask &tk = tasks[item.task];
         const int variant = __builtin_amdgcn_readfirstlane(tk.variant);

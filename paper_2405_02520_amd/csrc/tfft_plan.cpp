@@ -533,9 +533,11 @@ int shape_plan(tfft_plan_s *p, int64_t n, int64_t batch, int dtype, const tfft_o
     const int Guser = opt ? opt->group : 0;
     if (Guser < 0 || Guser > 64 || (Guser & (Guser - 1)) != 0) return TFFT_E_INVALID;
     if (opt && (opt->kappa < 0 || !std::isfinite(opt->kappa))) return TFFT_E_INVALID;
-    if (flags & ~(uint32_t)(TFFT_INVERSE_UNSCALED | TFFT_PERSISTENT | TFFT_PERSIST_INTERLEAVE)) return TFFT_E_INVALID;
+    if (flags & ~(uint32_t)(TFFT_INVERSE_UNSCALED | TFFT_PERSISTENT | TFFT_PERSIST_INTERLEAVE | TFFT_PERSIST_ONE_QUEUE))
+        return TFFT_E_INVALID;
     if ((flags & TFFT_PERSISTENT) && !ragged) return TFFT_E_INVALID;  // a ragged-batch mode
-    if ((flags & TFFT_PERSIST_INTERLEAVE) && !(flags & TFFT_PERSISTENT)) return TFFT_E_INVALID;
+    if ((flags & (TFFT_PERSIST_INTERLEAVE | TFFT_PERSIST_ONE_QUEUE)) && !(flags & TFFT_PERSISTENT))
+        return TFFT_E_INVALID;
     const int split = opt ? opt->split : 0;
     if (split < 0 || split > 1) return TFFT_E_INVALID;
     const int force_passes = opt ? opt->passes : 0;
@@ -946,6 +948,8 @@ struct tfft_ragged_s {
     int persistent = 0;
     int64_t item_tiles = 0;               // target tiles per work item (0: default)
     int item_interleave = 0;              // items of a chunk take every n-th group (1) or a range (0)
+    int n_queues = kPQueues;              // work queues (one per XCD, or 1)
+    int64_t *d_qbeg = nullptr;            // queue bounds, n_queues + 1
     std::vector<int> task_class, task_pass;
     std::vector<PItem> h_items;
     int n_done = 0;                       // release counters: one per (task, chunk)
@@ -1066,6 +1070,8 @@ void persist_free(tfft_ragged_s *r) {
     (void)hipFree(r->d_done);
     (void)hipFree(r->d_err);
     (void)hipFree(r->d_head);
+    (void)hipFree(r->d_qbeg);
+    r->d_qbeg = nullptr;
     (void)hipFree(r->d_rep);
     (void)hipFree(r->d_recs);
     r->d_items = nullptr;
@@ -1148,22 +1154,58 @@ int persist_build(tfft_ragged_s *r) {
     for (size_t c = 0; c < nc; ++c) order[c] = c;
     auto bytes = [&](size_t c) { return r->classes[c].n * (int64_t)r->classes[c].members.size(); };
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return bytes(a) > bytes(b); });
+    // Chunks to queues: every item of a chunk (all its passes) in one queue,
+    // so that a wait never crosses queues; the chunks, largest first, each to
+    // the queue with the fewest bytes so far.
+    const int nq = std::max(1, std::min(kPQueues, r->n_queues));
+    std::vector<std::vector<int>> qof(nc);
+    {
+        struct Ck {
+            size_t c;
+            int64_t q, bytes;
+        };
+        std::vector<Ck> cks;
+        for (size_t c = 0; c < nc; ++c) {
+            const tfft_plan_s *p = r->classes[c].plan;
+            const int64_t Q = class_chunk(p);
+            qof[c].assign((size_t)((p->batch + Q - 1) / Q), 0);
+            for (int64_t q = 0; q * Q < p->batch; ++q)
+                cks.push_back({c, q, std::min(Q, p->batch - q * Q) * r->classes[c].n * p->passes});
+        }
+        std::stable_sort(cks.begin(), cks.end(), [](const Ck &a, const Ck &b) { return a.bytes > b.bytes; });
+        std::vector<int64_t> load((size_t)nq, 0);
+        for (const Ck &k : cks) {
+            const size_t best = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+            qof[k.c][(size_t)k.q] = (int)best;
+            load[best] += k.bytes;
+        }
+    }
+    // each queue in level order: pass 0 of its multi-pass chunks (larger
+    // classes first), then pass 1, then pass 2, then its one-pass chunks
     r->h_items.clear();
-    for (int level = 0; level < kMaxPasses; ++level)
+    std::vector<int64_t> qbeg((size_t)kPQueues + 1, 0);
+    for (int k = 0; k < nq; ++k) {
+        qbeg[(size_t)k] = (int64_t)r->h_items.size();
+        for (int level = 0; level < kMaxPasses; ++level)
+            for (size_t c : order)
+                if (r->classes[c].plan->passes > 1 && level < r->classes[c].plan->passes)
+                    for (const PItem &it : per[(size_t)(task0[c] + level)])
+                        if (qof[c][(size_t)it.chunk] == k) r->h_items.push_back(it);
         for (size_t c : order)
-            if (r->classes[c].plan->passes > 1 && level < r->classes[c].plan->passes)
-                for (const PItem &it : per[(size_t)(task0[c] + level)]) r->h_items.push_back(it);
-    for (size_t c : order)
-        if (r->classes[c].plan->passes == 1)
-            for (const PItem &it : per[(size_t)task0[c]]) r->h_items.push_back(it);
+            if (r->classes[c].plan->passes == 1)
+                for (const PItem &it : per[(size_t)task0[c]])
+                    if (qof[c][(size_t)it.chunk] == k) r->h_items.push_back(it);
+    }
+    for (int k = nq; k <= kPQueues; ++k) qbeg[(size_t)k] = (int64_t)r->h_items.size();
     r->rec_cap = 0;
     for (auto &C : r->classes) r->rec_cap += C.plan->rec_cap;
     int rc = upload(&r->d_items, r->h_items);
     if (rc == TFFT_OK) rc = upload(&r->d_need, need);
+    if (rc == TFFT_OK) rc = upload(&r->d_qbeg, qbeg);
     if (rc == TFFT_OK && (hipMalloc((void **)&r->d_tasks, sizeof(PTask) * (size_t)std::max(1, ntask)) != hipSuccess ||
                           hipMalloc((void **)&r->d_done, sizeof(int32_t) * (size_t)std::max(1, nd)) != hipSuccess ||
                           hipMalloc((void **)&r->d_err, sizeof(int32_t)) != hipSuccess ||
-                          hipMalloc((void **)&r->d_head, sizeof(unsigned long long)) != hipSuccess ||
+                          hipMalloc((void **)&r->d_head, sizeof(unsigned long long) * kPQueues) != hipSuccess ||
                           hipMalloc((void **)&r->d_rep, sizeof(DevReport)) != hipSuccess ||
                           hipMalloc((void **)&r->d_recs, sizeof(DevRecord) * (size_t)r->rec_cap) != hipSuccess))
         rc = TFFT_E_NOMEM;
@@ -1213,6 +1255,9 @@ int persist_launch_all(tfft_ragged_s *r, int mode, hipStream_t st) {
     q.n_items = (int64_t)r->h_items.size();
     q.tasks = r->d_tasks;
     q.head = r->d_head;
+    q.q_begin = r->d_qbeg;
+    q.n_queues = std::max(1, std::min(kPQueues, r->n_queues));
+    q.pad_ = 0;
     q.done = r->d_done;
     q.need = r->d_need;
     q.err = r->d_err;
@@ -1315,6 +1360,18 @@ int persist_tune(tfft_ragged_s *r, const void *d_in, void *d_out, hipStream_t st
         }
     }
     r->item_interleave = best_il;
+    // one work queue per XCD, or a single one
+    int best_nq = r->n_queues;
+    for (int nq : {1, kPQueues}) {
+        if (status != TFFT_OK) break;
+        r->n_queues = nq;
+        float ms = 0.f;
+        if (persist_build(r) == TFFT_OK && time_all(&ms) == TFFT_OK && ms < best) {
+            best = ms;
+            best_nq = nq;
+        }
+    }
+    r->n_queues = best_nq;
     if (status == TFFT_OK) status = persist_build(r);
     // the new class plans get the faults installed on the old ones
     for (size_t ci = 0; ci < r->classes.size() && status == TFFT_OK; ++ci)
@@ -1373,6 +1430,7 @@ int tfft_ragged_create(tfft_ragged *out, int64_t count, const int64_t *lengths, 
     }
     r->persistent = (r->opt.flags & TFFT_PERSISTENT) ? 1 : 0;
     r->item_interleave = (r->opt.flags & TFFT_PERSIST_INTERLEAVE) ? 1 : 0;
+    r->n_queues = (r->opt.flags & TFFT_PERSIST_ONE_QUEUE) ? 1 : kPQueues;
     for (size_t c = 0; c < r->classes.size(); ++c) {
         const int rc = build_class(r, c, r->opt);
         if (rc != TFFT_OK) {

@@ -67,7 +67,8 @@ def test_plan_create_rejects_bad_arguments(tf, n, batch, dtype):
 def test_plan_create_rejects_bad_options(tf):
     h = ctypes.c_void_p()
     for group, kappa, flags in [(3, 0.0, 0), (128, 0.0, 0), (-1, 0.0, 0), (0, -1.0, 0), (0, float("nan"), 0),
-                                (0, 0.0, 1 << 7), (0, 0.0, tf.PERSISTENT), (0, 0.0, tf.PERSIST_INTERLEAVE)]:
+                                (0, 0.0, 1 << 7), (0, 0.0, tf.PERSISTENT), (0, 0.0, tf.PERSIST_INTERLEAVE),
+                                (0, 0.0, tf.PERSIST_ONE_QUEUE)]:
         opt = tf.tfft_options(flags=flags, group=group, kappa=kappa)
         assert tf.tfft_plan_create_with(ctypes.byref(h), 1024, 4, 0, ctypes.byref(opt)) == tf.E_INVALID
     assert tf.tfft_plan_create(None, 1024, 4, 0, 0) == tf.E_INVALID

@@ -85,12 +85,15 @@ def test_persistent_rejects_short_lengths(tf):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("gaps,interleave", [(False, False), (True, False), (False, True), (True, True)])
-def test_persistent_forward_matches_oracle(tf, dtype, gaps, interleave):
+@pytest.mark.parametrize("gaps,interleave,one_queue", [(False, False, False), (True, False, False),
+                                                       (False, True, False), (True, True, False),
+                                                       (True, False, True), (False, True, True)])
+def test_persistent_forward_matches_oracle(tf, dtype, gaps, interleave, one_queue):
     lengths, offsets, total = layout(inputs.SEED_RAGGED + 10, 300, 6, 16, gaps)
     x = inputs.uniform_flat(inputs.SEED_RAGGED + 10, total, NPDT[dtype])
-    print(f"persistent forward {dtype} gaps={gaps} interleave={interleave} total={total}", flush=True)
-    rg = tf.Ragged(lengths, offsets, dtype, persistent=True, interleave=interleave)
+    print(f"persistent forward {dtype} gaps={gaps} interleave={interleave} one_queue={one_queue} total={total}",
+          flush=True)
+    rg = tf.Ragged(lengths, offsets, dtype, persistent=True, interleave=interleave, one_queue=one_queue)
     xd = to_dev(x)
     out = to_dev(np.full(total, 7 + 7j, NPDT[dtype]))
     rg.forward(xd, out)
@@ -128,13 +131,15 @@ def test_persistent_equals_class_launches(tf, dtype):
     check_signals(x, yi, lengths, offsets, dtype, idx=range(0, 200, 3), inverse=True)
 
 
-@pytest.mark.parametrize("dtype,interleave", [("c64", False), ("c128", False), ("c64", True), ("c128", True)])
-def test_persistent_faults_are_corrected(tf, dtype, interleave):
+@pytest.mark.parametrize("dtype,interleave,one_queue", [("c64", False, False), ("c128", False, False),
+                                                        ("c64", True, False), ("c128", True, False),
+                                                        ("c64", False, True), ("c128", True, True)])
+def test_persistent_faults_are_corrected(tf, dtype, interleave, one_queue):
     lengths, offsets, total = layout(inputs.SEED_RAGGED + 12, 400, 6, 17, True)
     x = inputs.uniform_flat(inputs.SEED_RAGGED + 12, total, NPDT[dtype])
-    rg = tf.Ragged(lengths, offsets, dtype, persistent=True, interleave=interleave)
+    rg = tf.Ragged(lengths, offsets, dtype, persistent=True, interleave=interleave, one_queue=one_queue)
     specs, sigs = fault_specs(rg, lengths, inputs.fault_rng(inputs.SEED_RAGGED + 12), 0.03)
-    print(f"persistent faults {dtype} interleave={interleave}: {len(specs)}", flush=True)
+    print(f"persistent faults {dtype} interleave={interleave} one_queue={one_queue}: {len(specs)}", flush=True)
     rg.set_faults(specs)
     y = rg.forward(to_dev(x)).cpu().numpy()
     counts, recs = rg.report()
