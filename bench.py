@@ -63,6 +63,7 @@ def parse():
                          "one persistent launch, side by side")
     ap.add_argument("--class-log2", type=int, default=19, help="ragged-class: log2 of the signal length")
     ap.add_argument("--class-count", type=int, default=64, help="ragged-class: number of signals")
+    ap.add_argument("--tune", action="store_true", help="ragged-class: autotune both forms first")
     ap.add_argument("--ft", default="correct", choices=["off", "detect", "correct"],
                     help="fault-tolerance mode of the timed workload (the headline uses correct)")
     return ap.parse_args()
@@ -365,7 +366,7 @@ def bench_ragged(args):
     rg = tf.Ragged(lengths, dtype="c64", persistent=True)
     t0 = time.perf_counter()
     with torch.cuda.stream(st):
-        rg.tune(xd, out, reps=2)
+        rg.tune(xd, out, reps=3)
     st.synchronize()
     tune_s = time.perf_counter() - t0
 
@@ -521,6 +522,8 @@ def bench_ragged_class(args):
     for name, pers in (("per_class", False), ("persistent", True)):
         rg = tf.Ragged(lengths, dtype="c64", persistent=pers, interleave=pers)
         with torch.cuda.stream(st):
+            if args.tune:
+                rg.tune(xd, out, reps=2)
             for _ in range(max(1, args.warmup)):
                 rg.forward(xd, out, ft_mode=args.ft, use_graph=True)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -531,7 +534,7 @@ def bench_ragged_class(args):
         e1.synchronize()
         res[f"ms_{name}"] = round(e0.elapsed_time(e1) / args.steps, 4)
         rg.close()
-    print(json.dumps({"workload": "ragged-class", "n": n, "signals": args.class_count, "ft": args.ft,
+    print(json.dumps({"workload": "ragged-class", "n": n, "signals": args.class_count, "ft": args.ft, "tuned": args.tune,
                       "steps": args.steps, **res,
                       "ratio": round(res["ms_persistent"] / res["ms_per_class"], 3)}), flush=True)
 

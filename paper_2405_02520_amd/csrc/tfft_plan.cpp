@@ -11,6 +11,7 @@
 #include <complex>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <vector>
 
@@ -949,6 +950,7 @@ struct tfft_ragged_s {
     int64_t item_tiles = 0;               // target tiles per work item (0: default)
     int item_interleave = 0;              // items of a chunk take every n-th group (1) or a range (0)
     int n_queues = kPQueues;              // work queues (one per XCD, or 1)
+    int chunk_div = 8;                    // dependency chunks per class, about
     int64_t *d_qbeg = nullptr;            // queue bounds, n_queues + 1
     std::vector<int> task_class, task_pass;
     std::vector<PItem> h_items;
@@ -1048,10 +1050,10 @@ constexpr int64_t kPItemTiles = 32;  // default tiles per work item
 
 // Signals per dependency chunk of a class: a multiple of the signals every
 // pass's checksum group spans (so that no group straddles two chunks), at
-// most 64, and otherwise small enough for about 8 chunks per class (so that
-// a later pass starts on the first chunks while the last ones are still in
-// the previous pass).
-int64_t class_chunk(const tfft_plan_s *p) {
+// most 64, and otherwise small enough for about `div` chunks per class (so
+// that a later pass starts on the first chunks while the last ones are still
+// in the previous pass).
+int64_t class_chunk(const tfft_plan_s *p, int div) {
     int64_t span = 1;
     for (int i = 0; i < p->passes; ++i) {
         const PassPlan &P = p->pass[i];
@@ -1059,7 +1061,7 @@ int64_t class_chunk(const tfft_plan_s *p) {
         span = std::max(span, s);
     }
     int64_t q = 64;
-    while (q > span && q * 8 > p->batch) q /= 2;
+    while (q > span && q * div > p->batch) q /= 2;
     return std::max(q, span);
 }
 
@@ -1108,7 +1110,7 @@ int persist_build(tfft_ragged_s *r) {
     for (int t = 0; t < ntask; ++t) {
         done_base[t] = nd;
         const tfft_plan_s *pc = r->classes[(size_t)r->task_class[t]].plan;
-        const int64_t q = class_chunk(pc);
+        const int64_t q = class_chunk(pc, r->chunk_div);
         nd += (int)((pc->batch + q - 1) / q);
     }
     r->n_done = nd;
@@ -1124,7 +1126,7 @@ int persist_build(tfft_ragged_s *r) {
         const PassPlan &P = p->pass[r->task_pass[t]];
         const int64_t rounds = std::max(1, P.G / std::max(1, P.C));  // tiles per group
         const int64_t K = std::max<int64_t>(1, std::min<int64_t>(kPSlotCap, target / rounds));
-        const int64_t Q = class_chunk(p);
+        const int64_t Q = class_chunk(p, r->chunk_div);
         for (int64_t q = 0; q * Q < p->batch; ++q) {
             const ChunkGeom cg = chunk_geom(p, P, q * Q, std::min(Q, p->batch - q * Q));
             const int64_t n_it = (cg.n_groups + K - 1) / K;
@@ -1167,7 +1169,7 @@ int persist_build(tfft_ragged_s *r) {
         std::vector<Ck> cks;
         for (size_t c = 0; c < nc; ++c) {
             const tfft_plan_s *p = r->classes[c].plan;
-            const int64_t Q = class_chunk(p);
+            const int64_t Q = class_chunk(p, r->chunk_div);
             qof[c].assign((size_t)((p->batch + Q - 1) / Q), 0);
             for (int64_t q = 0; q * Q < p->batch; ++q)
                 cks.push_back({c, q, std::min(Q, p->batch - q * Q) * r->classes[c].n * p->passes});
@@ -1236,7 +1238,7 @@ int persist_tasks(tfft_ragged_s *r, const void *d_in, void *d_out, int mode, int
         k.done_base = nd;
         k.fix = mode == TFFT_FT_CORRECT;
         k.publish = i + 1 < p->passes;
-        nd += (int)((p->batch + class_chunk(p) - 1) / class_chunk(p));
+        nd += (int)((p->batch + class_chunk(p, r->chunk_div) - 1) / class_chunk(p, r->chunk_div));
     }
     if (hipMemcpy(r->d_tasks, tasks.data(), sizeof(PTask) * (size_t)ntask, hipMemcpyHostToDevice) != hipSuccess)
         return TFFT_E_HIP;
@@ -1336,42 +1338,28 @@ int persist_tune(tfft_ragged_s *r, const void *d_in, void *d_out, hipStream_t st
         status = build_class(r, ci, best_o);
         if (status == TFFT_OK) status = persist_build(r);
     }
-    // tiles per work item
-    int64_t best_ib = r->item_tiles;
-    for (int64_t ib : {int64_t(8), int64_t(16), int64_t(32), int64_t(64), int64_t(128)}) {
-        if (status != TFFT_OK) break;
-        r->item_tiles = ib;
-        float ms = 0.f;
-        if (persist_build(r) == TFFT_OK && time_all(&ms) == TFFT_OK && ms < best) {
-            best = ms;
-            best_ib = ib;
+    // The layout of the queue, one parameter at a time, each against a fresh
+    // measurement of every candidate (the current value among them): tiles
+    // per work item, item layout (range or interleaved), queues (one per XCD
+    // or one), dependency chunks per class (about 8 or about 32).
+    auto pick = [&](const std::vector<int64_t> &cands, const std::function<void(int64_t)> &set) {
+        int64_t bestv = cands.front();
+        float bestms = 3.4e38f;
+        for (int64_t v : cands) {
+            if (status != TFFT_OK) break;
+            set(v);
+            float ms = 0.f;
+            if (persist_build(r) == TFFT_OK && time_all(&ms) == TFFT_OK && ms < bestms) {
+                bestms = ms;
+                bestv = v;
+            }
         }
-    }
-    r->item_tiles = best_ib;
-    // contiguous or interleaved group ranges per item
-    int best_il = r->item_interleave;
-    for (int il : {0, 1}) {
-        if (status != TFFT_OK) break;
-        r->item_interleave = il;
-        float ms = 0.f;
-        if (persist_build(r) == TFFT_OK && time_all(&ms) == TFFT_OK && ms < best) {
-            best = ms;
-            best_il = il;
-        }
-    }
-    r->item_interleave = best_il;
-    // one work queue per XCD, or a single one
-    int best_nq = r->n_queues;
-    for (int nq : {1, kPQueues}) {
-        if (status != TFFT_OK) break;
-        r->n_queues = nq;
-        float ms = 0.f;
-        if (persist_build(r) == TFFT_OK && time_all(&ms) == TFFT_OK && ms < best) {
-            best = ms;
-            best_nq = nq;
-        }
-    }
-    r->n_queues = best_nq;
+        set(bestv);
+    };
+    pick({8, 16, 32, 64, 128}, [&](int64_t v) { r->item_tiles = v; });
+    pick({0, 1}, [&](int64_t v) { r->item_interleave = (int)v; });
+    pick({1, kPQueues}, [&](int64_t v) { r->n_queues = (int)v; });
+    pick({8, 32}, [&](int64_t v) { r->chunk_div = (int)v; });
     if (status == TFFT_OK) status = persist_build(r);
     // the new class plans get the faults installed on the old ones
     for (size_t ci = 0; ci < r->classes.size() && status == TFFT_OK; ++ci)
