@@ -1034,6 +1034,14 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, PassShared<R, M, KI
             }
             if constexpr (LDSPF && KIND == KIND_STRIDED)
                 asm volatile("" : "+v"(twA.re), "+v"(twA.im), "+v"(twB.re), "+v"(twB.im));
+            if constexpr (LDSPF && !ENC) {
+                // This tile's values read out of the DMA buffer before the next
+                // DMA is issued into it (the input encoding does the same for
+                // the checksummed tiles): with a read still pending at the
+                // DMA, the compiler waits for the DMA itself before using it.
+#pragma unroll
+                for (int m = 0; m < E; ++m) asm volatile("" : "+v"(d[m].re), "+v"(d[m].im));
+            }
             if constexpr (LDSPF) {
                 // Nothing older than the next tile's DMA outstanding in the
                 // compiler's count (the previous tile's deferred stores have
